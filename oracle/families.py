@@ -1,0 +1,314 @@
+"""Constraint families of the oracle: h(u), J(u), Hessian of lam^T h.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Variables of one sample are the discretized field flattened time-slab major,
+x fastest (2D: slab, then y, then x), as in the paper's worked Jacobian
+example (Appendix C).  Rows are in the canonical order documented per family;
+the GPU library returns its multipliers in the same order.
+
+Every function here is the definition written out with numpy/scipy.sparse;
+none of it is shared with the GPU code.
+
+Pins (tests/test_oracle_pins.py):
+  mass_ic     Appendix C printed 5x9 Jacobian; elementwise closed form.
+  fisher_kpp  logistic explicit-Euler trajectories are feasible; rho = 0 and
+              Nt = 2 reduce to closed-form hyperplane projections; J and the
+              Hessian against finite differences of h.
+  burgers_lf  consistency of the residual with the viscous Burgers PDE on an
+              exact travelling wave (residual/dt -> 0 under refinement);
+              telescoping of the flux differences; J and Hessian vs FD.
+  diff2d      consistency with the heat equation on a decaying Fourier mode;
+              single energy row = sphere projection (closed form); J/Hessian
+              vs FD.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY = 1, 2, 3, 4
+
+
+def _vid1(nx, k, i):
+    """flat index of u(x_i, t_k) in a 1D sample"""
+    return k * nx + i
+
+
+class MassIC:
+    """Initial condition + per-step mass (paper Table 1 rows 'Dirichlet IC' and
+    'Global mass conservation'; Heat-1 constraint set, Appendix A; Appendix C).
+
+    Canonical rows:
+      IC rows   u(x_i, t_0) - g_i                      i = 0..Nx-1
+      mass rows sum_i u(x_i, t_k) - M0                 k = 1..Nt-1
+    The t_0 mass row is left out (Appendix C omits the first-step mass row);
+    with the IC rows present it would be the sum of the IC rows.
+
+    encoding='appendix_c' gives the exact rows of the Appendix C example:
+      mass rows sum_{i < Nx-1} u(x_i, t_k) - sum_{i < Nx-1} u(x_i, t_0)
+    (left Riemann sum over the first Nx-1 points, relative to the first step).
+    """
+    types = ("ic", "mass")
+
+    def __init__(self, nx, nt, g, m0=None, encoding="plain"):
+        self.nx, self.nt = int(nx), int(nt)
+        self.g = np.asarray(g, dtype=np.float64)
+        self.m0 = float(self.g.sum() if m0 is None else m0)
+        self.encoding = encoding
+        self.n = self.nx * self.nt
+        self.m = self.nx + self.nt - 1
+
+    def h(self, u):
+        U = u.reshape(self.nt, self.nx)
+        ic = U[0] - self.g
+        if self.encoding == "appendix_c":
+            mass = U[1:, : self.nx - 1].sum(axis=1) - U[0, : self.nx - 1].sum()
+        else:
+            mass = U[1:].sum(axis=1) - self.m0
+        return np.concatenate([ic, mass])
+
+    def jac(self, u):
+        rows, cols, vals = [], [], []
+        for i in range(self.nx):
+            rows.append(i); cols.append(_vid1(self.nx, 0, i)); vals.append(1.0)
+        for k in range(1, self.nt):
+            r = self.nx + k - 1
+            if self.encoding == "appendix_c":
+                for i in range(self.nx - 1):
+                    rows.append(r); cols.append(_vid1(self.nx, k, i)); vals.append(1.0)
+                    rows.append(r); cols.append(_vid1(self.nx, 0, i)); vals.append(-1.0)
+            else:
+                for i in range(self.nx):
+                    rows.append(r); cols.append(_vid1(self.nx, k, i)); vals.append(1.0)
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.m, self.n))
+
+    def hess(self, u, lam):
+        return sp.csr_matrix((self.n, self.n))
+
+    def split(self, r):
+        return {"ic": r[: self.nx], "mass": r[self.nx:]}
+
+
+class FisherKPP:
+    """Initial condition + nonlinear mass budget of the logistic reaction
+    rho*u*(1-u) (paper Table 1 'Nonlinear conservation law'; reaction-diffusion
+    constraint set, Appendix A; time-discretized as in Appendix D, forward
+    difference in time of the spatial Riemann sum).  Periodic x, so no
+    boundary-flux term.
+
+    Canonical rows:
+      IC rows   u(x_i, t_0) - g_i                                        i = 0..Nx-1
+      law rows  sum_i u_i^{k+1} - sum_i u_i^k - dt*rho*sum_i u_i^k (1 - u_i^k)
+                                                                       k = 0..Nt-2
+    (The Appendix D form divides by dt and multiplies by dx; a row scaling
+    changes the multipliers, never the projected field.)
+    """
+    types = ("ic", "law")
+
+    def __init__(self, nx, nt, g, rho, dt):
+        self.nx, self.nt = int(nx), int(nt)
+        self.g = np.asarray(g, dtype=np.float64)
+        self.rho, self.dt = float(rho), float(dt)
+        self.n = self.nx * self.nt
+        self.m = self.nx + self.nt - 1
+
+    def h(self, u):
+        U = u.reshape(self.nt, self.nx)
+        ic = U[0] - self.g
+        mass = U.sum(axis=1)
+        react = (U * (1.0 - U)).sum(axis=1)
+        law = mass[1:] - mass[:-1] - self.dt * self.rho * react[:-1]
+        return np.concatenate([ic, law])
+
+    def jac(self, u):
+        U = u.reshape(self.nt, self.nx)
+        nx, nt = self.nx, self.nt
+        c = self.dt * self.rho
+        i = np.arange(nx)
+        k = np.arange(nt - 1)
+        K, I = np.meshgrid(k, i, indexing="ij")              # (nt-1, nx)
+        ic_r, ic_c, ic_v = i, _vid1(nx, 0, i), np.ones(nx)
+        # +1 on slab k+1
+        a_r, a_c, a_v = nx + K, _vid1(nx, K + 1, I), np.ones_like(K, dtype=float)
+        # -1 - dt*rho*(1 - 2u) on slab k
+        b_r, b_c = nx + K, _vid1(nx, K, I)
+        b_v = -1.0 - c * (1.0 - 2.0 * U[:-1])
+        rows = np.concatenate([ic_r, a_r.ravel(), b_r.ravel()])
+        cols = np.concatenate([ic_c, a_c.ravel(), b_c.ravel()])
+        vals = np.concatenate([ic_v, a_v.ravel(), b_v.ravel()])
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.m, self.n))
+
+    def hess(self, u, lam):
+        lam_law = np.asarray(lam[self.nx:])
+        d = np.zeros((self.nt, self.nx))
+        # d^2/du^2 of -dt*rho*u*(1-u) is +2*dt*rho on slab k of law row k
+        d[: self.nt - 1, :] = (2.0 * self.dt * self.rho * lam_law)[:, None]
+        return sp.diags(d.reshape(-1))
+
+    def split(self, r):
+        return {"ic": r[: self.nx], "law": r[self.nx:]}
+
+
+class BurgersLF:
+    """Local flux-update residuals of viscous Burgers u_t + (u^2/2)_x = nu*u_xx
+    on a periodic grid (paper Appendix D 'flux conservation': the residual is
+    the mismatch between consecutive steps and one conservative finite-volume
+    update; here with the smooth Lax-Friedrichs interface flux in place of the
+    Godunov flux, plus a centred viscous term).
+
+    Interface flux  F_{i+1/2} = (f(u_i) + f(u_{i+1}))/2 - (alpha/2)(u_{i+1} - u_i),
+    f(u) = u^2/2.  Canonical rows, k-major, for k = 0..Nt-2 and i = 0..Nx-1:
+      R_{k,i} = u_i^{k+1} - [ u_i^k - (dt/dx)(F_{i+1/2} - F_{i-1/2})
+                              + nu*dt*(u_{i+1} - 2u_i + u_{i-1})/dx^2 ]   (all at step k)
+    """
+    types = ("flux",)
+
+    def __init__(self, nx, nt, dt, dx, nu, alpha, advect=1.0):
+        self.nx, self.nt = int(nx), int(nt)
+        self.dt, self.dx, self.nu, self.alpha = float(dt), float(dx), float(nu), float(alpha)
+        # f(u) = advect * u^2 / 2; advect = 0 leaves the linear viscous scheme
+        self.advect = float(advect)
+        self.n = self.nx * self.nt
+        self.m = self.nx * (self.nt - 1)
+
+    def _flux(self, a, b):
+        return 0.25 * self.advect * (a * a + b * b) - 0.5 * self.alpha * (b - a)
+
+    def h(self, u):
+        U = u.reshape(self.nt, self.nx)
+        out = np.empty((self.nt - 1, self.nx))
+        r = self.dt / self.dx
+        v = self.nu * self.dt / (self.dx * self.dx)
+        for k in range(self.nt - 1):
+            uk = U[k]
+            up = np.roll(uk, -1)
+            um = np.roll(uk, 1)
+            Fp = self._flux(uk, up)       # F_{i+1/2}
+            Fm = self._flux(um, uk)       # F_{i-1/2}
+            update = uk - r * (Fp - Fm) + v * (up - 2.0 * uk + um)
+            out[k] = U[k + 1] - update
+        return out.reshape(-1)
+
+    def jac(self, u):
+        U = u.reshape(self.nt, self.nx)
+        r = self.dt / self.dx
+        v = self.nu * self.dt / (self.dx * self.dx)
+        a = self.alpha
+        nx, nt = self.nx, self.nt
+        K, I = np.meshgrid(np.arange(nt - 1), np.arange(nx), indexing="ij")
+        row = K * nx + I
+        ip, im = (I + 1) % nx, (I - 1) % nx
+        parts = [
+            # d/du_i^{k+1}
+            (row, _vid1(nx, K + 1, I), np.ones_like(row, dtype=float)),
+            # d/du_i^k: dF_{i+1/2}/du_i = u_i/2 + a/2, dF_{i-1/2}/du_i = u_i/2 - a/2
+            (row, _vid1(nx, K, I), np.full(row.shape, -1.0 + r * a + 2.0 * v)),
+            # d/du_{i+1}^k: r*dF_{i+1/2}/du_{i+1} - v = r*(u_{i+1}/2 - a/2) - v
+            (row, _vid1(nx, K, ip), r * (0.5 * self.advect * U[K, ip] - 0.5 * a) - v),
+            # d/du_{i-1}^k: -r*dF_{i-1/2}/du_{i-1} - v = -r*(u_{i-1}/2 + a/2) - v
+            (row, _vid1(nx, K, im), -r * (0.5 * self.advect * U[K, im] + 0.5 * a) - v),
+        ]
+        rows = np.concatenate([p[0].ravel() for p in parts])
+        cols = np.concatenate([p[1].ravel() for p in parts])
+        vals = np.concatenate([p[2].ravel() for p in parts])
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.m, self.n))
+
+    def hess(self, u, lam):
+        L = np.asarray(lam).reshape(self.nt - 1, self.nx)
+        half_r = 0.5 * self.advect * self.dt / self.dx
+        d = np.zeros((self.nt, self.nx))
+        for k in range(self.nt - 1):
+            # row (k,i) has +half_r*u_{i+1}^2/... : second derivative +half_r at i+1,
+            # -half_r at i-1
+            d[k] += half_r * np.roll(L[k], 1)     # lam_{k,j-1} at position j
+            d[k] -= half_r * np.roll(L[k], -1)    # lam_{k,j+1} at position j
+        return sp.diags(d.reshape(-1))
+
+    def split(self, r):
+        return {"flux": r}
+
+
+class Diff2DEnergy:
+    """2D periodic diffusion with a per-frame quadratic invariant (Navier-Stokes
+    analogue of Appendix A: local PDE residual rows as in the heat problem's
+    'u_t - alpha*u_xx' rows, and an enstrophy-type row int w^2 - const per
+    frame).
+
+    Grid: Nx x Ny periodic with spacing dx in both directions, 5-point
+    Laplacian Lap.  Canonical rows:
+      residual rows  u^{k+1}(p) - u^k(p) - dt*kappa*(Lap u^{k+1})(p)
+                     k = 0..Nt-2, p = (y, x) with x fastest
+      energy rows    sum_p u^t(p)^2 - E_t                          t = 0..Nt-1
+    """
+    types = ("residual", "energy")
+
+    def __init__(self, nx, ny, nt, dt, dx, kappa, energy):
+        self.nx, self.ny, self.nt = int(nx), int(ny), int(nt)
+        self.dt, self.dx, self.kappa = float(dt), float(dx), float(kappa)
+        self.E = np.asarray(energy, dtype=np.float64)
+        self.np_ = self.nx * self.ny
+        self.n = self.np_ * self.nt
+        self.m = (self.nt - 1) * self.np_ + self.nt
+
+    def _lap(self, f):
+        return (np.roll(f, 1, axis=0) + np.roll(f, -1, axis=0) + np.roll(f, 1, axis=1)
+                + np.roll(f, -1, axis=1) - 4.0 * f) / (self.dx * self.dx)
+
+    def h(self, u):
+        U = u.reshape(self.nt, self.ny, self.nx)
+        res = np.empty((self.nt - 1, self.ny, self.nx))
+        for k in range(self.nt - 1):
+            res[k] = U[k + 1] - U[k] - self.dt * self.kappa * self._lap(U[k + 1])
+        energy = (U * U).reshape(self.nt, -1).sum(axis=1) - self.E
+        return np.concatenate([res.reshape(-1), energy])
+
+    def jac(self, u):
+        U = u.reshape(self.nt, self.ny, self.nx)
+        nx, ny, npt, nt = self.nx, self.ny, self.np_, self.nt
+        s = self.dt * self.kappa / (self.dx * self.dx)
+        K, Y, X = np.meshgrid(np.arange(nt - 1), np.arange(ny), np.arange(nx), indexing="ij")
+        row = K * npt + Y * nx + X
+        nxt = (K + 1) * npt
+        parts = [(row, nxt + Y * nx + X, np.full(row.shape, 1.0 + 4.0 * s))]
+        for (yy, xx) in (((Y + 1) % ny, X), ((Y - 1) % ny, X), (Y, (X + 1) % nx), (Y, (X - 1) % nx)):
+            parts.append((row, nxt + yy * nx + xx, np.full(row.shape, -s)))
+        parts.append((row, K * npt + Y * nx + X, np.full(row.shape, -1.0)))
+        T, P = np.meshgrid(np.arange(nt), np.arange(npt), indexing="ij")
+        parts.append(((nt - 1) * npt + T, T * npt + P, 2.0 * U.reshape(nt, npt)))
+        rows = np.concatenate([p[0].ravel() for p in parts])
+        cols = np.concatenate([p[1].ravel() for p in parts])
+        vals = np.concatenate([p[2].ravel() for p in parts])
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.m, self.n))
+
+    def hess(self, u, lam):
+        lam_e = np.asarray(lam[(self.nt - 1) * self.np_:])
+        d = np.repeat(2.0 * lam_e, self.np_)
+        return sp.diags(d)
+
+    def split(self, r):
+        k = (self.nt - 1) * self.np_
+        return {"residual": r[:k], "energy": r[k:]}
+
+
+FAMILIES = {MASS_IC: MassIC, FISHER_KPP: FisherKPP, BURGERS_LF: BurgersLF,
+            DIFF2D_ENERGY: Diff2DEnergy}
+
+
+def family_of(sample, **kw):
+    """Build the oracle family object for one synthgen Sample."""
+    f = sample.family
+    if f == MASS_IC:
+        return MassIC(sample.nx, sample.nt, sample.aux[: sample.nx], sample.aux[sample.nx], **kw)
+    if f == FISHER_KPP:
+        return FisherKPP(sample.nx, sample.nt, sample.aux[: sample.nx], sample.p0, sample.dt)
+    if f == BURGERS_LF:
+        return BurgersLF(sample.nx, sample.nt, sample.dt, sample.dx, sample.p0, sample.p1)
+    if f == DIFF2D_ENERGY:
+        return Diff2DEnergy(sample.nx, sample.ny, sample.nt, sample.dt, sample.dx,
+                            sample.p0, sample.aux)
+    raise ValueError(f"unknown family {f}")
+
+
+def constraint_types(family: int):
+    return FAMILIES[family].types
