@@ -1,0 +1,184 @@
+/*
+ * snap.h -- C ABI of the batched constraint-projection library (gfx950).
+ *
+ * For every sample s of a batch, independently (the batch Jacobian is
+ * block-diagonal across samples, paper Sec. III-B), the library computes the
+ * projection step of the constrained flow-matching sampler (paper Sec. II-A,
+ * projection equation; restated as an NLP in Sec. III-B):
+ *
+ *     u*_s = argmin_u 1/2 ||u - u_hat_s||_2^2   subject to  h_s(u) = 0
+ *
+ * by Newton/SQP steps on the KKT system [[W, J^T], [J, 0]] (Appendix B), with
+ * W = I + sum_i lam_i Hess h_i.  The Lagrangian is 1/2||u - u_hat||^2 + lam^T h,
+ * so at the solution u* = u_hat - J(u*)^T lam*.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller unless
+ * stated otherwise; u, u_hat, lambda and gradients are float64.  Variables of
+ * one sample are the field flattened time-slab major, then y, then x (x
+ * fastest), as in the paper's Appendix C flattening.  Samples are packed
+ * back to back at the offsets given in their descriptors.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  snap_project
+ * and snap_project_backward only enqueue work and never synchronize.
+ *
+ * Errors: functions return SNAP_SUCCESS (0) or a negative SNAP_E* code for
+ * invalid arguments, unsupported shapes or HIP failures.  Non-convergence of
+ * a sample is not a call failure: it is reported per sample in the device
+ * array of snap_sample_stats (status field, SNAP_ST_*).
+ */
+#ifndef SNAP_H_
+#define SNAP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Constraint families (rows in canonical order; lambda is returned in it).
+ *
+ * SNAP_MASS_IC      initial condition + per-step mass (paper Table 1 'Dirichlet
+ *                   IC' and 'Global mass conservation'; Appendix A heat problem,
+ *                   Appendix C).  Rows: u(x_i,t_0) - g_i (i < Nx), then
+ *                   sum_i u(x_i,t_k) - M0 for k = 1..Nt-1.  aux = [g(Nx), M0].
+ * SNAP_FISHER_KPP   initial condition + logistic mass budget (Table 1 'Nonlinear
+ *                   conservation law'; Appendix A reaction-diffusion; Appendix D
+ *                   discretization).  Rows: IC as above, then
+ *                   sum u^{k+1} - sum u^k - dt*rho*sum u^k(1-u^k), k = 0..Nt-2.
+ *                   p0 = rho, dt = dt.  aux = [g(Nx)].
+ * SNAP_BURGERS_LF   flux-update residuals (Appendix D) of viscous Burgers with
+ *                   the Lax-Friedrichs interface flux, periodic x.  Rows (k,i),
+ *                   k-major, k = 0..Nt-2:  u_i^{k+1} - u_i^k + q(f(u_{i+1}^k) -
+ *                   f(u_{i-1}^k)) - c(u_{i+1}^k - 2u_i^k + u_{i-1}^k), f = u^2/2,
+ *                   q = dt/(2dx), c = p1*dt/(2dx) + p0*dt/dx^2.
+ *                   p0 = nu, p1 = alpha (flux speed).  No aux.
+ * SNAP_DIFF2D_ENERGY  reserved (2D diffusion + per-frame energy); not built.
+ */
+enum snap_family {
+  SNAP_MASS_IC = 1,
+  SNAP_FISHER_KPP = 2,
+  SNAP_BURGERS_LF = 3,
+  SNAP_DIFF2D_ENERGY = 4
+};
+
+enum snap_precision {
+  SNAP_PREC_FP64 = 0,   /* every step in float64 */
+  SNAP_PREC_MIXED = 1   /* float32 Schur factor/solve, float64 residuals and
+                           iterative refinement of every KKT solve */
+};
+
+enum snap_flags {
+  SNAP_FLAG_KEEP_FACTOR = 1  /* leave a factor of the KKT system taken at the
+                                returned point in the workspace, for
+                                snap_project_backward */
+};
+
+/* call-level return codes */
+enum snap_error {
+  SNAP_SUCCESS = 0,
+  SNAP_EINVAL = -1,        /* bad argument (null pointer, bad size, bad option) */
+  SNAP_EHIP = -2,          /* a HIP runtime call or kernel launch failed */
+  SNAP_ENOMEM = -3,        /* plan creation could not allocate its metadata */
+  SNAP_EUNSUPPORTED = -4   /* family or grid size not supported */
+};
+
+/* per-sample status codes (snap_sample_stats.status) */
+enum snap_sample_status {
+  SNAP_ST_CONVERGED = 0,      /* ||h||_inf <= tol_h and stationarity <= tol_s(1+||u_hat||_inf) */
+  SNAP_ST_MAX_ITER = 1,       /* max_newton iterations without meeting the tolerances */
+  SNAP_ST_LS_FAIL = 2,        /* line search found no decrease of the merit */
+  SNAP_ST_NONFINITE = 3,      /* NaN/Inf in input or iterates */
+  SNAP_ST_SINGULAR_PIVOT = 4  /* non-positive pivot in the Schur factorization */
+};
+
+/* One sample.  Offsets are element offsets into the packed arrays. */
+typedef struct snap_sample_desc {
+  int32_t family;      /* enum snap_family */
+  int32_t nx, ny, nt;  /* grid; ny = 1 in 1D */
+  double dt, dx;       /* time step, grid spacing */
+  double p0, p1;       /* family parameters (see enum snap_family) */
+  int64_t var_off;     /* offset of the sample's variables in u_hat / u / gradients */
+  int64_t row_off;     /* offset of its multipliers in lambda */
+  int64_t aux_off;     /* offset of its auxiliary data in aux */
+} snap_sample_desc;
+
+typedef struct snap_options {
+  double tol_h;        /* feasibility tolerance on ||h(u)||_inf (e.g. 1e-10) */
+  double tol_s;        /* stationarity tolerance, relative to 1 + ||u_hat||_inf */
+  int32_t max_newton;  /* Newton iterations per sample (>= 1) */
+  int32_t max_ls;      /* backtracking halvings per line search (>= 0) */
+  int32_t precision;   /* enum snap_precision */
+  int32_t flags;       /* enum snap_flags, or-ed */
+} snap_options;
+
+typedef struct snap_sample_stats {
+  int32_t status;         /* enum snap_sample_status */
+  int32_t newton_iters;   /* Newton steps taken */
+  int32_t ls_backtracks;  /* total step halvings */
+  int32_t refine_steps;   /* iterative-refinement corrections (mixed precision) */
+  double h_inf;           /* ||h(u)||_inf at the returned point */
+  double stat_inf;        /* ||u - u_hat + J^T lambda||_inf at the returned point */
+} snap_sample_stats;
+
+typedef struct snap_plan_s* snap_plan;
+
+/* Fill *opt with the defaults: tol_h 1e-10, tol_s 1e-10, max_newton 20,
+ * max_ls 30, FP64, no flags. */
+void snap_default_options(snap_options* opt);
+
+/* Create a plan for `batch` samples described by the HOST array descs_host
+ * (copied; the caller may free it).  The plan fixes the sparsity structure,
+ * row orderings and band widths once (the fixed pattern is reused across
+ * iterations and calls, paper Sec. III-B/III-C), and allocates its own small
+ * device metadata on the current device.  batch = 0 is valid (calls then do
+ * nothing).  Returns SNAP_EUNSUPPORTED for families or sizes the library does
+ * not build.  Thread-safe: a plan is immutable after creation. */
+int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* descs_host,
+                     const snap_options* opt);
+
+/* Bytes of caller-owned device workspace that snap_project and
+ * snap_project_backward need for this plan (256-byte aligned start required). */
+int snap_plan_workspace_bytes(snap_plan plan, size_t* bytes);
+
+/* Number of constraint rows / variables / aux values the plan expects in the
+ * packed arrays. */
+int snap_plan_sizes(snap_plan plan, int64_t* total_vars, int64_t* total_rows, int64_t* total_aux);
+
+/* Forward projection of every sample.
+ *   uhat        [total_vars]  input (read only)
+ *   aux         [total_aux]   family data (IC targets, masses); may be NULL if total_aux = 0
+ *   u_out       [total_vars]  projected fields (must not alias uhat)
+ *   lambda_out  [total_rows]  multipliers, canonical row order
+ *   stats       [batch]       per-sample status and diagnostics
+ *   workspace   snap_plan_workspace_bytes bytes, 256-byte aligned
+ * With SNAP_FLAG_KEEP_FACTOR in the plan's options, the workspace afterwards
+ * holds the Schur factor at the returned (u, lambda) for the backward call. */
+int snap_project(snap_plan plan, const double* uhat, const double* aux, double* u_out,
+                 double* lambda_out, snap_sample_stats* stats, void* workspace, void* stream);
+
+/* Vector-Jacobian product of the projection with respect to u_hat at the
+ * solution (implicit-function theorem on the KKT conditions): with the KKT
+ * matrix K at (u, lambda), grad_uhat is the u-block of K^{-1} [grad_u; 0]
+ * = W^{-1}(grad_u - J^T b) with (J W^{-1} J^T) b = J W^{-1} grad_u.
+ *   u, lambda   outputs of snap_project on the same plan and workspace
+ *   grad_u      [total_vars]  upstream gradient
+ *   grad_uhat   [total_vars]  result
+ *   stats       [batch]       refine_steps and status of the adjoint solve
+ * Reuses the factor left by a forward call with SNAP_FLAG_KEEP_FACTOR; without
+ * it the library factors again at (u, lambda). */
+int snap_project_backward(snap_plan plan, const double* u, const double* lambda,
+                          const double* aux, void* workspace, const double* grad_u,
+                          double* grad_uhat, snap_sample_stats* stats, void* stream);
+
+int snap_plan_destroy(snap_plan plan);
+
+/* Static strings for return codes (negative) and sample status codes (>= 0). */
+const char* snap_error_string(int code);
+const char* snap_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAP_H_ */

@@ -1,0 +1,278 @@
+// Host side of the C ABI declared in include/snap.h: plan construction
+// (shapes, groupings, workspace layout; the sparsity structure is fixed once,
+// as the paper exploits for repeated factorizations, Sec. III-B/III-C), and
+// stream-ordered launches of the family kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "snap.h"
+#include "snap_device.hpp"
+
+namespace snap {
+int slab_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st);
+bool slab_supported(int nx, int nt);
+int band_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st);
+bool band_supported(int nx, int nt, bool mixed);
+size_t band_workspace_bytes(int nx, int nt, bool mixed);
+}  // namespace snap
+
+using namespace snap;
+
+namespace {
+
+struct Group {
+  int family, nx, nt;
+  std::vector<int32_t> ids;
+  int32_t* d_ids = nullptr;
+};
+
+}  // namespace
+
+struct snap_plan_s {
+  int32_t batch = 0;
+  snap_options opt{};
+  std::vector<snap_sample_desc> descs;
+  snap_sample_desc* d_descs = nullptr;
+  std::vector<Group> groups;
+  std::vector<int64_t> ws_off;   // per-sample byte offsets
+  int64_t* d_ws_off = nullptr;
+  size_t ws_bytes = 0;
+  int64_t total_vars = 0, total_rows = 0, total_aux = 0;
+  int device = 0;
+};
+
+namespace {
+
+int64_t rows_of(const snap_sample_desc& d) {
+  switch (d.family) {
+    case SNAP_MASS_IC:
+    case SNAP_FISHER_KPP: return (int64_t)d.nx + d.nt - 1;
+    case SNAP_BURGERS_LF: return (int64_t)d.nx * (d.nt - 1);
+    default: return -1;
+  }
+}
+
+int64_t aux_of(const snap_sample_desc& d) {
+  switch (d.family) {
+    case SNAP_MASS_IC: return d.nx + 1;
+    case SNAP_FISHER_KPP: return d.nx;
+    default: return 0;
+  }
+}
+
+void free_plan(snap_plan p) {
+  if (!p) return;
+  for (auto& g : p->groups)
+    if (g.d_ids) (void)hipFree(g.d_ids);
+  if (p->d_descs) (void)hipFree(p->d_descs);
+  if (p->d_ws_off) (void)hipFree(p->d_ws_off);
+  delete p;
+}
+
+bool options_valid(const snap_options& o) {
+  return o.tol_h > 0 && o.tol_s > 0 && o.max_newton >= 1 && o.max_ls >= 0 &&
+         (o.precision == SNAP_PREC_FP64 || o.precision == SNAP_PREC_MIXED);
+}
+
+}  // namespace
+
+extern "C" {
+
+void snap_default_options(snap_options* opt) {
+  if (!opt) return;
+  opt->tol_h = 1e-10;
+  opt->tol_s = 1e-10;
+  opt->max_newton = 20;
+  opt->max_ls = 30;
+  opt->precision = SNAP_PREC_FP64;
+  opt->flags = 0;
+}
+
+int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* descs_host,
+                     const snap_options* opt) {
+  if (!out || batch < 0 || (batch > 0 && !descs_host)) return SNAP_EINVAL;
+  *out = nullptr;
+  snap_options o;
+  if (opt) o = *opt; else snap_default_options(&o);
+  if (!options_valid(o)) return SNAP_EINVAL;
+  const bool mixed = o.precision == SNAP_PREC_MIXED;
+
+  snap_plan p = new (std::nothrow) snap_plan_s();
+  if (!p) return SNAP_ENOMEM;
+  p->batch = batch;
+  p->opt = o;
+  p->descs.assign(descs_host, descs_host + batch);
+  if (hipGetDevice(&p->device) != hipSuccess) { free_plan(p); return SNAP_EHIP; }
+
+  std::map<std::tuple<int, int, int>, size_t> gidx;
+  p->ws_off.assign(batch, 0);
+  size_t ws = 0;
+  for (int32_t s = 0; s < batch; ++s) {
+    const snap_sample_desc& d = p->descs[s];
+    if (d.nx < 1 || d.nt < 1 || d.ny != 1 || d.var_off < 0 || d.row_off < 0 || d.aux_off < 0) {
+      free_plan(p); return SNAP_EINVAL;
+    }
+    const int64_t m = rows_of(d);
+    if (m < 0) { free_plan(p); return SNAP_EUNSUPPORTED; }
+    bool ok = false;
+    size_t need = 0;
+    if (d.family == SNAP_MASS_IC || d.family == SNAP_FISHER_KPP) {
+      ok = slab_supported(d.nx, d.nt);
+      if (d.family == SNAP_FISHER_KPP && !(d.dt > 0.0)) ok = false;
+    } else if (d.family == SNAP_BURGERS_LF) {
+      ok = band_supported(d.nx, d.nt, mixed) && d.dt > 0.0 && d.dx > 0.0;
+      need = band_workspace_bytes(d.nx, d.nt, mixed);
+    }
+    if (!ok) { free_plan(p); return SNAP_EUNSUPPORTED; }
+    p->ws_off[s] = (int64_t)ws;
+    ws += (need + 255) & ~(size_t)255;
+    const int64_t nvar = (int64_t)d.nx * d.ny * d.nt;
+    p->total_vars = std::max(p->total_vars, d.var_off + nvar);
+    p->total_rows = std::max(p->total_rows, d.row_off + m);
+    p->total_aux = std::max(p->total_aux, d.aux_off + aux_of(d));
+    auto key = std::make_tuple(d.family, d.nx, d.nt);
+    auto it = gidx.find(key);
+    if (it == gidx.end()) {
+      gidx[key] = p->groups.size();
+      p->groups.push_back(Group{d.family, d.nx, d.nt, {}, nullptr});
+      p->groups.back().ids.push_back(s);
+    } else {
+      p->groups[it->second].ids.push_back(s);
+    }
+  }
+  p->ws_bytes = std::max<size_t>(ws, 256);
+
+  if (batch > 0) {
+    if (hipMalloc(&p->d_descs, sizeof(snap_sample_desc) * batch) != hipSuccess ||
+        hipMemcpy(p->d_descs, p->descs.data(), sizeof(snap_sample_desc) * batch,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc(&p->d_ws_off, sizeof(int64_t) * batch) != hipSuccess ||
+        hipMemcpy(p->d_ws_off, p->ws_off.data(), sizeof(int64_t) * batch,
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      free_plan(p); return SNAP_ENOMEM;
+    }
+    for (auto& g : p->groups) {
+      if (hipMalloc(&g.d_ids, sizeof(int32_t) * g.ids.size()) != hipSuccess ||
+          hipMemcpy(g.d_ids, g.ids.data(), sizeof(int32_t) * g.ids.size(),
+                    hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(p); return SNAP_ENOMEM;
+      }
+    }
+  }
+  *out = p;
+  return SNAP_SUCCESS;
+}
+
+int snap_plan_workspace_bytes(snap_plan plan, size_t* bytes) {
+  if (!plan || !bytes) return SNAP_EINVAL;
+  *bytes = plan->ws_bytes;
+  return SNAP_SUCCESS;
+}
+
+int snap_plan_sizes(snap_plan plan, int64_t* total_vars, int64_t* total_rows, int64_t* total_aux) {
+  if (!plan) return SNAP_EINVAL;
+  if (total_vars) *total_vars = plan->total_vars;
+  if (total_rows) *total_rows = plan->total_rows;
+  if (total_aux) *total_aux = plan->total_aux;
+  return SNAP_SUCCESS;
+}
+
+static int run(snap_plan plan, KernelArgs a, hipStream_t st) {
+  const bool mixed = plan->opt.precision == SNAP_PREC_MIXED;
+  for (auto& g : plan->groups) {
+    a.order = g.d_ids;
+    a.count = (int32_t)g.ids.size();
+    int rc = SNAP_EUNSUPPORTED;
+    if (g.family == SNAP_MASS_IC || g.family == SNAP_FISHER_KPP)
+      rc = slab_launch(a, g.nx, g.nt, mixed, st);
+    else if (g.family == SNAP_BURGERS_LF)
+      rc = band_launch(a, g.nx, g.nt, mixed, st);
+    if (rc != 0) return rc;
+  }
+  return SNAP_SUCCESS;
+}
+
+int snap_project(snap_plan plan, const double* uhat, const double* aux, double* u_out,
+                 double* lambda_out, snap_sample_stats* stats, void* workspace, void* stream) {
+  if (!plan) return SNAP_EINVAL;
+  if (plan->batch == 0) return SNAP_SUCCESS;
+  if (!uhat || !u_out || !lambda_out || !stats || !workspace) return SNAP_EINVAL;
+  if (plan->total_aux > 0 && !aux) return SNAP_EINVAL;
+  if (u_out == uhat) return SNAP_EINVAL;
+  if (((uintptr_t)workspace & 255) != 0) return SNAP_EINVAL;
+  KernelArgs a{};
+  a.descs = plan->d_descs;
+  a.uhat = uhat;
+  a.aux = aux;
+  a.u = u_out;
+  a.lam = lambda_out;
+  a.stats = stats;
+  a.ws = (unsigned char*)workspace;
+  a.ws_off = plan->d_ws_off;
+  a.opt = plan->opt;
+  a.backward = 0;
+  return run(plan, a, (hipStream_t)stream);
+}
+
+int snap_project_backward(snap_plan plan, const double* u, const double* lambda, const double* aux,
+                          void* workspace, const double* grad_u, double* grad_uhat,
+                          snap_sample_stats* stats, void* stream) {
+  if (!plan) return SNAP_EINVAL;
+  if (plan->batch == 0) return SNAP_SUCCESS;
+  if (!u || !lambda || !grad_u || !grad_uhat || !stats || !workspace) return SNAP_EINVAL;
+  if (((uintptr_t)workspace & 255) != 0) return SNAP_EINVAL;
+  KernelArgs a{};
+  a.descs = plan->d_descs;
+  a.uhat = nullptr;
+  a.aux = aux;
+  a.u = const_cast<double*>(u);
+  a.lam = const_cast<double*>(lambda);
+  a.stats = stats;
+  a.grad_u = grad_u;
+  a.grad_uhat = grad_uhat;
+  a.ws = (unsigned char*)workspace;
+  a.ws_off = plan->d_ws_off;
+  a.opt = plan->opt;
+  a.backward = 1;
+  if (plan->total_aux > 0 && !aux) {
+    // the slab kernels read aux (IC targets) unconditionally
+    return SNAP_EINVAL;
+  }
+  return run(plan, a, (hipStream_t)stream);
+}
+
+int snap_plan_destroy(snap_plan plan) {
+  if (!plan) return SNAP_EINVAL;
+  free_plan(plan);
+  return SNAP_SUCCESS;
+}
+
+const char* snap_error_string(int code) {
+  switch (code) {
+    case SNAP_SUCCESS: return "success";
+    case SNAP_EINVAL: return "invalid argument";
+    case SNAP_EHIP: return "HIP runtime error";
+    case SNAP_ENOMEM: return "out of memory";
+    case SNAP_EUNSUPPORTED: return "unsupported family or size";
+    default: return "unknown error";
+  }
+}
+
+const char* snap_status_string(int status) {
+  switch (status) {
+    case SNAP_ST_CONVERGED: return "converged";
+    case SNAP_ST_MAX_ITER: return "max_iter";
+    case SNAP_ST_LS_FAIL: return "line_search_failed";
+    case SNAP_ST_NONFINITE: return "nonfinite";
+    case SNAP_ST_SINGULAR_PIVOT: return "singular_pivot";
+    default: return "unknown";
+  }
+}
+
+}  // extern "C"

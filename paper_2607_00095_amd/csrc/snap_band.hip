@@ -1,0 +1,870 @@
+// Newton/SQP projection for local flux-residual constraints (viscous Burgers,
+// Lax-Friedrichs flux, periodic x): the banded Schur-complement path.
+//
+// Rows (k, x), k = 0..Nt-2, involve u(x, k+1) and u(x-1..x+1, k) (paper
+// Appendix D flux residual; Sec. III-B: local couplings give a sparse, here
+// banded, Jacobian).  With W = I + Hess(lam^T h) (diagonal: the flux is
+// separable), the Newton-KKT system of Appendix B reduces to
+//     S lam+ = h - J W^{-1}(u - u_hat),   S = J W^{-1} J^T,
+//     p = -W^{-1}(u - u_hat + J^T lam+).
+// S is symmetric positive definite and, with rows ordered slab-major and
+// "folded" inside a slab (x = 0, Nx-1, 1, Nx-2, ...: periodic neighbours end up
+// at most two positions apart), banded with half-bandwidth b = Nx + 2.
+//
+// Factorization: S = L D L^T by a right-looking block-band LDL^T with 16x16
+// blocks (block half-bandwidth BB = ceil(b/16)).  One workgroup per sample.
+// The live window (block rows J..J+BB) lives in MFMA accumulator registers:
+// block (I, I-d) is kept in slot (d, I mod (BB+1-d)), a fixed owner, so a
+// retiring panel block is replaced in place by the entering block of row
+// J+BB+1.  Per panel J:
+//   1. the diagonal block is factored in registers by one wavefront (16 lanes,
+//      one row each), giving L_JJ, D_J, L_JJ^{-1} and T = L_JJ^{-T} D_J^{-1};
+//   2. panel blocks L(I,J) = S(I,J) T   (MFMA);
+//   3. trailing update S(I,K) -= L(I,J) D_J L(K,J)^T   (MFMA, rank 16);
+//   4. the entering block row is assembled from the stencil (S is never
+//      stored unfactored) and the forward substitution L y = r advances.
+// The factor (L_JJ^{-1}, L(I,J), D) is written to the workspace for the
+// backward substitution and for the adjoint.
+//
+// Precision R: double (plain form) or float (mixed form: float32 factor and
+// solves, float64 residual r - S x from the stencil, iterative refinement).
+#include "snap_device.hpp"
+
+namespace snap {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+  using V = dvec4;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using V = fvec4;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kT = 16;              // block size
+constexpr int kLd = 17;             // padded LDS row stride (bank-conflict free column reads)
+constexpr int kTL = kT * kLd;       // LDS words per tile
+constexpr double kWFloor = 0.1;
+
+__device__ __forceinline__ int fold_x(int p, int nx) { return (p & 1) ? nx - 1 - (p >> 1) : (p >> 1); }
+__device__ __forceinline__ int pos_of(int x, int nx) {
+  return (2 * x <= nx - 1) ? 2 * x : 2 * (nx - 1 - x) + 1;
+}
+__device__ __forceinline__ int wrap(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+
+template <int BB, int NW, typename R>
+struct BandShared {
+  R P[BB + 1][kTL];        // panel blocks (S, then L after the panel solve)
+  R NR[BB + 1][kTL];       // staging area of the entering block row
+  R T[kTL];                // L_JJ^{-T} D_J^{-1}
+  double Lw[kTL];          // diagonal block -> L_JJ (unit lower) with D on the diagonal
+  double Xw[kTL];          // L_JJ^{-1}
+  double Dv[kT];
+  double ring[(BB + 1) * kT];   // right-hand side / solution window of live block rows
+  double newr[kT];
+  double yJ[kT];
+  double part[NW * kWave];
+  double red[NW][4];
+  int flag[4];
+};
+
+// Per-sample view: geometry, pointers, stencil coefficients.
+struct Ctx {
+  int nx, nt, m, n, M, NB;
+  double q, c, cd;           // f-coefficient dt/(2dx), diffusion number, -1 + 2c
+  bool bwd;
+  const double* uh;          // u_hat (forward)
+  const double* g;           // upstream gradient (backward)
+  double* u;                 // current iterate (forward) / u* (backward)
+  double* lam;               // current multipliers (canonical order)
+  unsigned char* ws;
+};
+
+// workspace layout of one sample (byte offsets, 256-aligned)
+struct WsLayout {
+  size_t hdr, L, Dg, Y, rin, rvec, lamp, p, t, res, total;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+__host__ __device__ inline int band_bb(int nx, int nt) {
+  int b = nt > 2 ? nx + 2 : 4;
+  if (b < 4) b = 4;
+  return (b + kT - 1) / kT;
+}
+
+__host__ __device__ inline WsLayout ws_layout(int nx, int nt, int BB, size_t rsize) {
+  WsLayout w;
+  const size_t m = (size_t)nx * (nt - 1), n = (size_t)nx * nt;
+  const size_t M = (m + kT - 1) / kT * kT, NB = M / kT;
+  size_t o = 0;
+  w.hdr = o; o += 256;
+  w.L = o; o += align256(NB * (BB + 1) * 256 * rsize);
+  w.Dg = o; o += align256(M * 8);
+  w.Y = o; o += align256(M * 8);
+  w.rin = o; o += align256(M * 8);
+  w.rvec = o; o += align256(m * 8);
+  w.lamp = o; o += align256(m * 8);
+  w.p = o; o += align256(n * 8);
+  w.t = o; o += align256(n * 8);
+  w.res = o; o += align256(m * 8);
+  w.total = o;
+  return w;
+}
+
+// ------------------------------------------------------------------ stencil
+// d(v) = u - u_hat (forward), -g (backward)
+__device__ __forceinline__ double dres(const Ctx& C, int v) {
+  return C.bwd ? -C.g[v] : C.u[v] - C.uh[v];
+}
+
+// W at variable (k, x) from the current multipliers
+__device__ __forceinline__ double w_at(const Ctx& C, int k, int x) {
+  if (k > C.nt - 2) return 1.0;
+  const double* L = C.lam + (size_t)k * C.nx;
+  double w = 1.0 + C.q * (L[wrap(x - 1, C.nx)] - L[wrap(x + 1, C.nx)]);
+  return fmax(w, kWFloor);
+}
+
+// h of row (k, x)
+__device__ __forceinline__ double h_row(const Ctx& C, int k, int x) {
+  const double* U = C.u + (size_t)k * C.nx;
+  const double up = U[wrap(x + 1, C.nx)], um = U[wrap(x - 1, C.nx)], u0 = U[x];
+  return C.u[(size_t)(k + 1) * C.nx + x] - u0 + 0.5 * C.q * (up * up - um * um) -
+         C.c * (up - 2.0 * u0 + um);
+}
+
+// (J^T y)(k, x) for a row-space vector y in canonical order
+__device__ __forceinline__ double jt_at(const Ctx& C, const double* y, int k, int x) {
+  const int nx = C.nx;
+  double s = 0.0;
+  if (k >= 1) s += y[(size_t)(k - 1) * nx + x];
+  if (k <= C.nt - 2) {
+    const double uu = C.u[(size_t)k * nx + x];
+    const double* Y = y + (size_t)k * nx;
+    s += (C.q * uu - C.c) * Y[wrap(x - 1, nx)];     // row (k, x-1): its +1 neighbour is x
+    s += C.cd * Y[x];
+    s += (-C.q * uu - C.c) * Y[wrap(x + 1, nx)];    // row (k, x+1): its -1 neighbour is x
+  }
+  return s;
+}
+
+// (J z)(row k, x) for a variable-space vector z
+__device__ __forceinline__ double j_at(const Ctx& C, const double* z, int k, int x) {
+  const int nx = C.nx;
+  const double* U = C.u + (size_t)k * nx;
+  const double* Z = z + (size_t)k * nx;
+  const int xp = wrap(x + 1, nx), xm = wrap(x - 1, nx);
+  return z[(size_t)(k + 1) * nx + x] + C.cd * Z[x] + (C.q * U[xp] - C.c) * Z[xp] +
+         (-C.q * U[xm] - C.c) * Z[xm];
+}
+
+// ------------------------------------------------------------------ reductions
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double (*red)[4], int slot) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w][slot] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) s += red[q][slot];
+  __syncthreads();
+  return s;
+}
+
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double (*red)[4], int slot) {
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w][slot] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW; ++q) s = fmax(s, red[q][slot]);
+  __syncthreads();
+  return s;
+}
+
+// ------------------------------------------------------------------ assembly
+// Row r (internal order) of S and of the right-hand side h - J W^{-1} d,
+// scattered into the staging tile row `a` for columns [lo, hi) (block-aligned):
+// S[r, r'] = sum over variables v of row r of J(r,v) J(r',v) / W(v).
+template <int BB, typename R>
+__device__ __forceinline__ void scatter_s(const Ctx& C, int I, int a, int lo, int hi, R (*NR)[kTL],
+                                          int rk, int rx, double val) {
+  const int col = rk * C.nx + pos_of(rx, C.nx);
+  if (col >= lo && col < hi) {
+    const int cb = col / kT, cc = col - cb * kT;
+    NR[I - cb][a * kLd + cc] += (R)val;
+  }
+}
+
+template <int BB, typename R>
+__device__ void assemble_row(const Ctx& C, int r, int a, int I, R (*NR)[kTL], double* rhs_out,
+                             double* rvec, double* rin) {
+  const int nx = C.nx;
+  if (r >= C.M) { *rhs_out = 0.0; return; }
+  if (r >= C.m) {            // padding row: identity
+    NR[0][a * kLd + a] = (R)1.0;
+    *rhs_out = 0.0;
+    rin[r] = 0.0;
+    return;
+  }
+  const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
+  const int lo = (I - BB) * kT, hi = (I + 1) * kT;
+  double rhs = C.bwd ? 0.0 : h_row(C, k, x);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    // the four variables of row (k, x): (k+1, x), (k, x), (k, x+1), (k, x-1)
+    const int kk = (e == 0) ? k + 1 : k;
+    const int y = (e <= 1) ? x : (e == 2 ? wrap(x + 1, nx) : wrap(x - 1, nx));
+    const size_t v = (size_t)kk * nx + y;
+    const double uy = C.u[v];
+    const double al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
+    const double s = al / w_at(C, kk, y);
+    rhs -= s * dres(C, (int)v);
+    // rows touching variable (kk, y): (kk-1, y) with 1; (kk, y-1), (kk, y), (kk, y+1)
+    if (kk >= 1) scatter_s<BB, R>(C, I, a, lo, hi, NR, kk - 1, y, s);
+    if (kk <= C.nt - 2) {
+      scatter_s<BB, R>(C, I, a, lo, hi, NR, kk, wrap(y - 1, nx), s * (C.q * uy - C.c));
+      scatter_s<BB, R>(C, I, a, lo, hi, NR, kk, y, s * C.cd);
+      scatter_s<BB, R>(C, I, a, lo, hi, NR, kk, wrap(y + 1, nx), s * (-C.q * uy - C.c));
+    }
+  }
+  *rhs_out = rhs;
+  rvec[(size_t)k * nx + x] = rhs;
+  rin[r] = rhs;
+}
+
+// ------------------------------------------------------------------ factor
+// Factor S at the current (u, lam) with the fused forward substitution of the
+// right-hand side; writes L blocks, D, y = L^{-1} r, rvec (canonical rhs) and
+// rin (internal-order rhs).  Returns 1 if a non-positive pivot was met.
+template <int BB, int NW, typename R>
+__device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh) {
+  using V = typename Mfma<R>::V;
+  constexpr int NS = (BB + 1) * (BB + 2) / 2;
+  constexpr int SPW = (NS + NW - 1) / NW;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+  const int li = lane & 15, lk = lane >> 4;
+  R* Lg = (R*)(C.ws + WL.L);
+  double* Dg = (double*)(C.ws + WL.Dg);
+  double* Y = (double*)(C.ws + WL.Y);
+  double* rvec = (double*)(C.ws + WL.rvec);
+  double* rin = (double*)(C.ws + WL.rin);
+
+  // slot metadata: slot id = w + NW*s -> (d, sidx)
+  int sd[SPW], ss[SPW];
+#pragma unroll
+  for (int s = 0; s < SPW; ++s) {
+    int id = w + NW * s;
+    int d = -1, sidx = 0;
+    if (id < NS) {
+      int base = 0;
+      for (int dd = 0; dd <= BB; ++dd) {
+        int cnt = BB + 1 - dd;
+        if (id < base + cnt) { d = dd; sidx = id - base; break; }
+        base += cnt;
+      }
+    }
+    sd[s] = d; ss[s] = sidx;
+  }
+  auto slot_row = [&](int s, int J) -> int {   // block row I held by slot s at step J
+    const int d = sd[s], P = BB + 1 - d;
+    int t = (ss[s] - J - d) % P;
+    if (t < 0) t += P;
+    return J + d + t;
+  };
+
+  V acc[SPW];
+#pragma unroll
+  for (int s = 0; s < SPW; ++s) acc[s] = V{0, 0, 0, 0};
+
+  auto zero_nr = [&]() {
+    R* z = &sh.NR[0][0];
+    for (int i = threadIdx.x; i < (BB + 1) * kTL; i += NW * kWave) z[i] = (R)0;
+  };
+  auto load_nr = [&](int s, int d) {
+    V v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = sh.NR[d][(4 * lk + e) * kLd + li];
+    acc[s] = v;
+  };
+
+  // ---- initial window: block rows 0..BB
+  for (int I = 0; I <= BB; ++I) {
+    zero_nr();
+    __syncthreads();
+    if (threadIdx.x < kT) {
+      double rr;
+      assemble_row<BB, R>(C, I * kT + threadIdx.x, threadIdx.x, I, sh.NR, &rr, rvec, rin);
+      sh.ring[(I % (BB + 1)) * kT + threadIdx.x] = (I < C.NB) ? rr : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < SPW; ++s)
+      if (sd[s] >= 0 && sd[s] <= I && slot_row(s, 0) == I) load_nr(s, sd[s]);
+    __syncthreads();
+  }
+
+  int bad = 0;
+  for (int J = 0; J < C.NB; ++J) {
+    // (a) gather the panel column J into LDS; clear the staging area
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      if (sd[s] < 0) continue;
+      if (slot_row(s, J) - sd[s] == J) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sh.P[sd[s]][(4 * lk + e) * kLd + li] = acc[s][e];
+      }
+    }
+    zero_nr();
+    __syncthreads();
+
+    // (b) wavefront 0: LDL^T of the diagonal block; wavefront 1: next block row
+    if (w == 0) {
+      // LDL^T of the 16x16 diagonal block in LDS by one wavefront: lane owns
+      // entries (li, 4*lk + e).  Right-looking; runtime loops keep registers low.
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = 4 * lk + e;
+        sh.Lw[li * kLd + k] = (double)sh.P[0][li * kLd + k];
+      }
+      wave_sync();
+      int nonpos = 0;
+      for (int p = 0; p < kT; ++p) {
+        const double dp = sh.Lw[p * kLd + p];
+        nonpos |= !(dp > 0.0);
+        const double lip = sh.Lw[li * kLd + p] / dp;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = 4 * lk + e;
+          if (li > p && k > p) sh.Lw[li * kLd + k] -= lip * sh.Lw[k * kLd + p];
+        }
+        wave_sync();
+        if (lane < kT && lane > p) sh.Lw[lane * kLd + p] = lip;
+        wave_sync();
+      }
+      // X = L_JJ^{-1} by forward elimination on the identity
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int cc = 4 * lk + e;
+        sh.Xw[li * kLd + cc] = (li == cc) ? 1.0 : 0.0;
+      }
+      if (lane < kT) {
+        sh.Dv[lane] = sh.Lw[lane * kLd + lane];
+        Dg[(size_t)J * kT + lane] = sh.Lw[lane * kLd + lane];
+      }
+      wave_sync();
+      for (int k = 0; k < kT - 1; ++k) {
+        const double lik = sh.Lw[li * kLd + k];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int cc = 4 * lk + e;
+          if (li > k && cc <= k) sh.Xw[li * kLd + cc] -= lik * sh.Xw[k * kLd + cc];
+        }
+        wave_sync();
+      }
+      // T = L^{-T} D^{-1}: T[r][c] = X[c][r] / D_c ; global copy of X
+      R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int cc = 4 * lk + e;
+        sh.T[li * kLd + cc] = (R)(sh.Xw[cc * kLd + li] / sh.Dv[cc]);
+        Lgd[li * kT + cc] = (R)sh.Xw[li * kLd + cc];
+      }
+      if (lane < kT) {
+        const double* rJ = &sh.ring[(J % (BB + 1)) * kT];
+        double y = 0.0;
+        for (int cc = 0; cc < kT; ++cc) y += sh.Xw[lane * kLd + cc] * rJ[cc];
+        sh.yJ[lane] = y;
+        Y[(size_t)J * kT + lane] = y;
+      }
+      nonpos = __any(nonpos);
+      if (lane == 0 && nonpos) sh.flag[0] = 1;
+    } else if (w == 1 && lane < kT) {
+      const int I = J + BB + 1;
+      double rr = 0.0;
+      if (I < C.NB) assemble_row<BB, R>(C, I * kT + lane, lane, I, sh.NR, &rr, rvec, rin);
+      sh.newr[lane] = rr;
+    }
+    __syncthreads();
+
+    // (c) panel solve L(J+d, J) = S(J+d, J) T for d >= 1
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      const int d = sd[s];
+      if (d < 1) continue;
+      if (slot_row(s, J) - d != J) continue;
+      V res = V{0, 0, 0, 0};
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const R av = sh.P[d][li * kLd + 4 * qq + lk];
+        const R bv = sh.T[(4 * qq + lk) * kLd + li];
+        res = Mfma<R>::mma(av, bv, res);
+      }
+      R* Lgd = Lg + ((size_t)J * (BB + 1) + d) * 256;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        sh.P[d][(4 * lk + e) * kLd + li] = res[e];
+        Lgd[(4 * lk + e) * kT + li] = res[e];
+      }
+    }
+    __syncthreads();
+
+    // (d) forward-substitution update, trailing update, entering row
+    for (int t = threadIdx.x; t < kT * BB; t += NW * kWave) {
+      const int d = 1 + t / kT, a = t - (d - 1) * kT;
+      const int I = J + d;
+      if (I < C.NB) {
+        double s = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < kT; ++cc) s += (double)sh.P[d][a * kLd + cc] * sh.yJ[cc];
+        sh.ring[(I % (BB + 1)) * kT + a] -= s;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      const int d = sd[s];
+      if (d < 0) continue;
+      const int I = slot_row(s, J), K = I - d;
+      if (K == J) {
+        load_nr(s, d);                       // retire panel block, take the entering one
+      } else {
+        const int di = I - J, dk = K - J;    // 1 <= dk <= di <= BB
+        V v = acc[s];
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const R av = -sh.P[di][li * kLd + 4 * qq + lk];
+          const R bv = (R)sh.Dv[4 * qq + lk] * sh.P[dk][li * kLd + 4 * qq + lk];
+          v = Mfma<R>::mma(av, bv, v);
+        }
+        acc[s] = v;
+      }
+      // keep the scheduler from hoisting every slot's operand loads at once
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (threadIdx.x < kT) sh.ring[(J % (BB + 1)) * kT + threadIdx.x] = sh.newr[threadIdx.x];
+    __syncthreads();
+  }
+  bad = sh.flag[0];
+  __syncthreads();
+  if (threadIdx.x == 0) sh.flag[0] = 0;
+  __syncthreads();
+  return bad;
+}
+
+// ------------------------------------------------------------------ solves
+// forward substitution y = L^{-1} rin with the stored factor
+template <int BB, int NW, typename R>
+__device__ __attribute__((always_inline)) void forward_sweep(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh,
+                              const double* rin, double* Y) {
+  const R* Lg = (const R*)(C.ws + WL.L);
+  for (int t = threadIdx.x; t < (BB + 1) * kT; t += NW * kWave) {
+    const int I = t / kT, a = t - I * kT;
+    sh.ring[t] = (I < C.NB) ? rin[(size_t)I * kT + a] : 0.0;
+  }
+  __syncthreads();
+  for (int J = 0; J < C.NB; ++J) {
+    const R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
+    if (threadIdx.x < kT) {
+      const double* rJ = &sh.ring[(J % (BB + 1)) * kT];
+      const int i = threadIdx.x;
+      double y = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < kT; ++cc) y += (double)Lgd[i * kT + cc] * rJ[cc];
+      sh.yJ[i] = y;
+      Y[(size_t)J * kT + i] = y;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kT * BB; t += NW * kWave) {
+      const int d = 1 + t / kT, a = t - (d - 1) * kT;
+      const int I = J + d;
+      if (I < C.NB) {
+        const R* Lb = Lgd + (size_t)d * 256 + a * kT;
+        double s = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < kT; ++cc) s += (double)Lb[cc] * sh.yJ[cc];
+        sh.ring[(I % (BB + 1)) * kT + a] -= s;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kT) {
+      const int I = J + BB + 1;
+      sh.ring[(J % (BB + 1)) * kT + threadIdx.x] = (I < C.NB) ? rin[(size_t)I * kT + threadIdx.x] : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// backward substitution x = L^{-T} D^{-1} Y; x is written in canonical row order
+template <int BB, int NW, typename R>
+__device__ __attribute__((always_inline)) void backward_sweep(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh,
+                               const double* Y, double* xout) {
+  const R* Lg = (const R*)(C.ws + WL.L);
+  const double* Dg = (const double*)(C.ws + WL.Dg);
+  const int t = threadIdx.x;
+  const int cc = t & 15, grp = t >> 4;        // column of the block, partial-sum group
+  constexpr int NG = NW * kWave / kT;          // groups of 16 threads
+  for (int i = t; i < (BB + 1) * kT; i += NW * kWave) sh.ring[i] = 0.0;
+  __syncthreads();
+  for (int J = C.NB - 1; J >= 0; --J) {
+    const R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
+    // partial sums of sum_{d,a} L(J+d,J)[a][c] x_{J+d}[a] over (d, a) pairs
+    double s = 0.0;
+    for (int pq = grp; pq < BB * kT; pq += NG) {
+      const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
+      if (J + d < C.NB)
+        s += (double)Lgd[(size_t)d * 256 + a * kT + cc] * sh.ring[((J + d) % (BB + 1)) * kT + a];
+    }
+    sh.part[t] = s;
+    __syncthreads();
+    if (t < kT) {
+      double acc = 0.0;
+      for (int q = 0; q < NG; ++q) acc += sh.part[q * kT + t];
+      sh.yJ[t] = Y[(size_t)J * kT + t] / Dg[(size_t)J * kT + t] - acc;
+    }
+    __syncthreads();
+    if (t < kT) {
+      double x = 0.0;
+#pragma unroll
+      for (int c2 = 0; c2 < kT; ++c2) x += (double)Lgd[c2 * kT + t] * sh.yJ[c2];   // L^{-T}
+      sh.ring[(J % (BB + 1)) * kT + t] = x;
+      const int r = J * kT + t;
+      if (r < C.m) {
+        const int k = r / C.nx, px = r - k * C.nx;
+        xout[(size_t)k * C.nx + fold_x(px, C.nx)] = x;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// res = rvec - S x (float64, matrix free), x canonical; returns max |res|
+template <int NW>
+__device__ double schur_residual(const Ctx& C, const WsLayout& WL, const double* x, double* res,
+                                 double (*red)[4]) {
+  double* tv = (double*)(C.ws + WL.t);
+  const double* rvec = (const double*)(C.ws + WL.rvec);
+  for (int v = threadIdx.x; v < C.n; v += NW * kWave) {
+    const int k = v / C.nx, xx = v - k * C.nx;
+    tv[v] = jt_at(C, x, k, xx) / w_at(C, k, xx);
+  }
+  __syncthreads();
+  double mx = 0.0;
+  for (int r = threadIdx.x; r < C.m; r += NW * kWave) {
+    const int k = r / C.nx, xx = r - k * C.nx;
+    const double v = rvec[r] - j_at(C, tv, k, xx);
+    res[r] = v;
+    mx = fmax(mx, fabs(v));
+  }
+  return block_max<NW>(mx, red, 0);
+}
+
+// canonical row vector -> internal-order right-hand side
+template <int NW>
+__device__ void to_internal(const Ctx& C, const double* canon, double* rin) {
+  for (int r = threadIdx.x; r < C.M; r += NW * kWave) {
+    double v = 0.0;
+    if (r < C.m) {
+      const int k = r / C.nx, px = r - k * C.nx;
+      v = canon[(size_t)k * C.nx + fold_x(px, C.nx)];
+    }
+    rin[r] = v;
+  }
+  __syncthreads();
+}
+
+// Solve S x = rhs given the factor (rhs in rin / rvec; y of the fused forward
+// pass already in Y when have_y), with float64 iterative refinement in the
+// mixed form.  Each sweep has a single call site.
+template <int BB, int NW, typename R>
+__device__ __attribute__((always_inline)) int solve_with_factor(
+    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, bool have_y, double* x) {
+  double* Y = (double*)(C.ws + WL.Y);
+  double* rin = (double*)(C.ws + WL.rin);
+  double* res = (double*)(C.ws + WL.res);
+  double* dx = (double*)(C.ws + WL.t);          // correction (t is free between residuals)
+  const double* rvec = (const double*)(C.ws + WL.rvec);
+  constexpr bool plain = sizeof(R) == sizeof(double);
+  double rn = 0.0;
+  if (!plain) {
+    for (int r = threadIdx.x; r < C.m; r += NW * kWave) rn = fmax(rn, fabs(rvec[r]));
+    rn = block_max<NW>(rn, sh.red, 1);
+  }
+  int refines = 0;
+  for (int it = 0; it < 7; ++it) {
+    if (it > 0 || !have_y) forward_sweep<BB, NW, R>(C, WL, sh, rin, Y);
+    backward_sweep<BB, NW, R>(C, WL, sh, Y, it == 0 ? x : dx);
+    if (it > 0) {
+      for (int r = threadIdx.x; r < C.m; r += NW * kWave) x[r] += dx[r];
+      __syncthreads();
+      ++refines;
+    }
+    if (plain) break;
+    const double rm = schur_residual<NW>(C, WL, x, res, sh.red);
+    if (!(rm > 1e-13 * rn)) break;
+    to_internal<NW>(C, res, rin);
+  }
+  return refines;
+}
+
+// ------------------------------------------------------------------ kernel
+template <int BB, int NW, typename R, bool BWD>
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void band_kernel(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  Ctx C;
+  C.nx = D.nx; C.nt = D.nt;
+  C.m = D.nx * (D.nt - 1);
+  C.n = D.nx * D.nt;
+  C.M = (C.m + kT - 1) / kT * kT;
+  C.NB = C.M / kT;
+  C.q = 0.5 * D.dt / D.dx;
+  C.c = D.p1 * D.dt / (2.0 * D.dx) + D.p0 * D.dt / (D.dx * D.dx);
+  C.cd = -1.0 + 2.0 * C.c;
+  C.bwd = BWD;
+  C.uh = A.uhat ? A.uhat + D.var_off : nullptr;
+  C.g = A.grad_u ? A.grad_u + D.var_off : nullptr;
+  C.u = A.u + D.var_off;
+  C.lam = A.lam + D.row_off;
+  C.ws = A.ws + A.ws_off[sid];
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  int* hdr = (int*)(C.ws + WL.hdr);
+  double* lamp = (double*)(C.ws + WL.lamp);
+  double* pv = (double*)(C.ws + WL.p);
+  const int NT = NW * kWave;
+  const bool keep = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0;
+  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+
+  int status = SNAP_ST_MAX_ITER, iters = 0, backtracks = 0, refines = 0;
+  double hinf = 0.0, stinf = 0.0;
+
+  if constexpr (BWD) {
+    // adjoint: S b = J W^{-1} g, grad = W^{-1}(g - J^T b), at (u*, lam*)
+    double* rin = (double*)(C.ws + WL.rin);
+    double* rvec = (double*)(C.ws + WL.rvec);
+    const bool have = keep && hdr[0] == 1;
+    __syncthreads();
+    int bad = 0;
+    if (have) {
+      for (int r = threadIdx.x; r < C.M; r += NT) {
+        double v = 0.0;
+        if (r < C.m) {
+          const int k = r / C.nx, px = r - k * C.nx, x = fold_x(px, C.nx);
+          // rhs = -J W^{-1} d with d = -g
+          double s = 0.0;
+          const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
+          const double* U = C.u + (size_t)k * C.nx;
+          s += C.g[(size_t)(k + 1) * C.nx + x] / w_at(C, k + 1, x);
+          s += C.cd * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
+          s += (C.q * U[xp] - C.c) * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
+          s += (-C.q * U[xm] - C.c) * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
+          v = s;
+          rvec[(size_t)k * C.nx + x] = s;
+        }
+        rin[r] = v;
+      }
+      __syncthreads();
+    } else {
+      bad = factor_sweep<BB, NW, R>(C, WL, sh);
+    }
+    refines = solve_with_factor<BB, NW, R>(C, WL, sh, !have, lamp);
+    __syncthreads();
+    for (int v = threadIdx.x; v < C.n; v += NT) {
+      const int k = v / C.nx, x = v - k * C.nx;
+      A.grad_uhat[D.var_off + v] = (C.g[v] - jt_at(C, lamp, k, x)) / w_at(C, k, x);
+    }
+    if (threadIdx.x == 0) {
+      snap_sample_stats st;
+      st.status = bad ? SNAP_ST_SINGULAR_PIVOT : SNAP_ST_CONVERGED;
+      st.newton_iters = 0; st.ls_backtracks = 0; st.refine_steps = refines;
+      st.h_inf = 0.0; st.stat_inf = 0.0;
+      A.stats[sid] = st;
+    }
+    return;
+  } else {
+
+  // ---------------------------------------------------------------- forward
+  double umax = 0.0;
+  int nonfin = 0;
+  for (int v = threadIdx.x; v < C.n; v += NT) {
+    const double x = C.uh[v];
+    C.u[v] = x;
+    umax = fmax(umax, fabs(x));
+    nonfin |= !finite(x);
+  }
+  for (int r = threadIdx.x; r < C.m; r += NT) C.lam[r] = 0.0;
+  if (threadIdx.x == 0) hdr[0] = 0;
+  const double uscale = 1.0 + block_max<NW>(umax, sh.red, 0);
+  if (block_max<NW>((double)nonfin, sh.red, 1) > 0.0) status = SNAP_ST_NONFINITE;
+  double mu = 0.0;
+
+  for (int it = 0; status != SNAP_ST_NONFINITE; ++it) {
+    // ---- evaluate h, stationarity and the objective at (u, lam)
+    double hm = 0.0, h1 = 0.0, sm = 0.0, f0 = 0.0;
+    for (int v = threadIdx.x; v < C.n; v += NT) {
+      const int k = v / C.nx, x = v - k * C.nx;
+      const double d = dres(C, v);
+      f0 += 0.5 * d * d;
+      sm = fmax(sm, fabs(d + jt_at(C, C.lam, k, x)));
+      if (k <= C.nt - 2) {
+        const double h = h_row(C, k, x);
+        hm = fmax(hm, fabs(h));
+        h1 += fabs(h);
+        if (!finite(h)) hm = __builtin_nan("");
+      }
+    }
+    hm = block_max<NW>(hm, sh.red, 0);
+    sm = block_max<NW>(sm, sh.red, 1);
+    h1 = block_sum<NW>(h1, sh.red, 2);
+    f0 = block_sum<NW>(f0, sh.red, 3);
+    hinf = hm; stinf = sm;
+    if (!finite(hm) || !finite(sm)) { status = SNAP_ST_NONFINITE; break; }
+    const bool conv = hm <= A.opt.tol_h && sm <= A.opt.tol_s * uscale;
+    if (conv && !keep) { status = SNAP_ST_CONVERGED; break; }
+    if (!conv && it >= A.opt.max_newton) { status = SNAP_ST_MAX_ITER; break; }
+
+    // ---- Schur factor (at the returned point too when the adjoint needs it)
+    const int bad = factor_sweep<BB, NW, R>(C, WL, sh);
+    if (conv) {
+      status = SNAP_ST_CONVERGED;
+      if (threadIdx.x == 0) hdr[0] = bad ? 0 : 1;
+      break;
+    }
+    if (bad) { status = SNAP_ST_SINGULAR_PIVOT; break; }
+    refines += solve_with_factor<BB, NW, R>(C, WL, sh, true, lamp);
+    __syncthreads();
+
+    // ---- step p = -W^{-1}(d + J^T lam+), merit derivative
+    double dd = 0.0, lmax = 0.0;
+    for (int v = threadIdx.x; v < C.n; v += NT) {
+      const int k = v / C.nx, x = v - k * C.nx;
+      const double d = dres(C, v);
+      const double p = -(d + jt_at(C, lamp, k, x)) / w_at(C, k, x);
+      pv[v] = p;
+      dd += d * p;
+    }
+    for (int r = threadIdx.x; r < C.m; r += NT) lmax = fmax(lmax, fabs(lamp[r]));
+    dd = block_sum<NW>(dd, sh.red, 0);
+    lmax = block_max<NW>(lmax, sh.red, 1);
+    mu = fmax(mu, 1.1 * lmax + 1e-8);
+    const double phi0 = f0 + mu * h1;
+    const double dphi = dd - mu * h1;
+
+    // ---- backtracking on the l1 merit; trial points are evaluated without
+    //      touching u (h of u + alpha p from the stencil)
+    double alpha = 1.0;
+    int ok = 0;
+    for (int ls = 0; ls <= A.opt.max_ls; ++ls) {
+      double ft = 0.0, ht = 0.0;
+      for (int v = threadIdx.x; v < C.n; v += NT) {
+        const int k = v / C.nx, x = v - k * C.nx;
+        const double dt_ = dres(C, v) + alpha * pv[v];
+        ft += 0.5 * dt_ * dt_;
+        if (k <= C.nt - 2) {
+          const size_t b0 = (size_t)k * C.nx;
+          const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
+          const double u0 = C.u[b0 + x] + alpha * pv[b0 + x];
+          const double up = C.u[b0 + xp] + alpha * pv[b0 + xp];
+          const double um = C.u[b0 + xm] + alpha * pv[b0 + xm];
+          const double un = C.u[b0 + C.nx + x] + alpha * pv[b0 + C.nx + x];
+          const double h = un - u0 + 0.5 * C.q * (up * up - um * um) - C.c * (up - 2.0 * u0 + um);
+          ht += fabs(h);
+        }
+      }
+      ft = block_sum<NW>(ft, sh.red, 0);
+      ht = block_sum<NW>(ht, sh.red, 1);
+      const double phi = ft + mu * ht;
+      if (phi <= phi0 + 1e-4 * alpha * dphi + 1e-13 * fabs(phi0) || !(dphi < 0.0)) { ok = 1; break; }
+      alpha *= 0.5;
+      ++backtracks;
+    }
+    if (!ok) { status = SNAP_ST_LS_FAIL; break; }
+    for (int v = threadIdx.x; v < C.n; v += NT) C.u[v] += alpha * pv[v];
+    for (int r = threadIdx.x; r < C.m; r += NT) C.lam[r] += alpha * (lamp[r] - C.lam[r]);
+    __syncthreads();
+    ++iters;
+  }
+
+  if (threadIdx.x == 0) {
+    snap_sample_stats st;
+    st.status = status;
+    st.newton_iters = iters;
+    st.ls_backtracks = backtracks;
+    st.refine_steps = refines;
+    st.h_inf = hinf;
+    st.stat_inf = stinf;
+    A.stats[sid] = st;
+  }
+}
+}
+
+// ------------------------------------------------------------------ dispatch
+static const int kBBs[] = {1, 2, 3, 5, 7, 9, 13, 17};
+
+static int pick_bb(int need) {
+  for (int b : kBBs)
+    if (b >= need) return b;
+  return -1;
+}
+
+template <int BB, typename R>
+static void launch_band(const KernelArgs& a, hipStream_t st) {
+  constexpr int NW = BB <= 9 ? 4 : 8;
+  if (a.backward)
+    hipLaunchKernelGGL((band_kernel<BB, NW, R, true>), dim3(a.count), dim3(NW * kWave), 0, st, a);
+  else
+    hipLaunchKernelGGL((band_kernel<BB, NW, R, false>), dim3(a.count), dim3(NW * kWave), 0, st, a);
+}
+
+template <typename R>
+static int launch_bb(int bb, const KernelArgs& a, hipStream_t st) {
+#ifdef SNAP_BAND_QUICK
+  if (bb <= SNAP_BAND_QUICK) { launch_band<SNAP_BAND_QUICK, R>(a, st); return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP; }
+  return SNAP_EUNSUPPORTED;
+#else
+  switch (bb) {
+    case 1: launch_band<1, R>(a, st); break;
+    case 2: launch_band<2, R>(a, st); break;
+    case 3: launch_band<3, R>(a, st); break;
+    case 5: launch_band<5, R>(a, st); break;
+    case 7: launch_band<7, R>(a, st); break;
+    case 9: launch_band<9, R>(a, st); break;
+    case 13: launch_band<13, R>(a, st); break;
+    case 17: launch_band<17, R>(a, st); break;
+    default: return SNAP_EUNSUPPORTED;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP;
+#endif
+}
+
+bool band_supported(int nx, int nt, bool mixed) {
+  (void)mixed;
+  return nx >= 3 && nt >= 2 && pick_bb(band_bb(nx, nt)) > 0 && (int64_t)nx * nt < (1 << 30);
+}
+
+size_t band_workspace_bytes(int nx, int nt, bool mixed) {
+  const int bb = pick_bb(band_bb(nx, nt));
+  return ws_layout(nx, nt, bb, mixed ? sizeof(float) : sizeof(double)).total;
+}
+
+int band_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st) {
+  if (a.count == 0) return 0;
+  if (!band_supported(nx, nt, mixed)) return SNAP_EUNSUPPORTED;
+  const int bb = pick_bb(band_bb(nx, nt));
+  return mixed ? launch_bb<float>(bb, a, st) : launch_bb<double>(bb, a, st);
+}
+
+}  // namespace snap

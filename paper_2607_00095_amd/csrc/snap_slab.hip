@@ -1,0 +1,554 @@
+// Newton/SQP projection for the "slab-row" families: constraints that are
+// global in x and local in time (paper Sec. III-A: mass-type rows touch one or
+// two time slabs), plus initial-condition rows on slab 0.
+//
+//   SNAP_MASS_IC     rows sum_x u(.,k+1) - M0                   (k = 0..Nt-2)
+//   SNAP_FISHER_KPP  rows sum_x u(.,k+1) - sum_x u(.,k) - dt*rho*sum_x u(.,k)(1-u(.,k))
+//
+// Both are written as row_k = sum_x b*u(x,k+1) + (terms in slab k), with
+// b = 1 and a_k(x) = d row_k / d u(x,k) (0 for mass rows).  The Hessian of
+// lam^T h is diagonal and constant on a slab (2*dt*rho*lam_k on slab k), so
+// W = I + Hess(lam^T h) is one number W_k per slab.
+//
+// Schur form of the Newton-KKT system (Appendix B) with u-step
+// p = -W^{-1}(u - u_hat + J^T lam+):   S lam+ = h - J W^{-1}(u - u_hat),
+// S = J W^{-1} J^T.  With IC rows first, S = [[D, C], [C^T, T]]:
+//   D_ii = 1/W_0,   C_{i,0} = a_0(i)/W_0,
+//   T_kk = sum_x a_k^2/W_k + Nx/W_{k+1},  T_{k,k+1} = sum_x a_{k+1}/W_{k+1}.
+// Eliminating the diagonal IC block cancels the slab-0 term of T_00 exactly,
+// leaving a symmetric tridiagonal system in time, solved by parallel cyclic
+// reduction inside one wavefront.
+//
+// One workgroup (8 wavefronts) owns one sample for the whole Newton loop.
+// Wavefront w owns time slabs w, w+8, ...; lane l owns x = l, l+64, ...; the
+// field stays in registers and every slab sum is a wavefront reduction.
+#include "snap_device.hpp"
+
+namespace snap {
+
+constexpr int kSlabWaves = 8;
+constexpr int kSlabThreads = kSlabWaves * kWave;
+constexpr int kMaxNt = 128;
+
+template <typename TS>
+struct PcrBuf {
+  TS a[2][kMaxNt], b[2][kMaxNt], c[2][kMaxNt], d[2][kMaxNt];
+};
+
+// Parallel cyclic reduction of the symmetric tridiagonal system
+// diag Td[0..n), off-diagonal To[k] = T_{k,k+1}, right-hand side rhs, by ONE
+// wavefront (n <= 128, two equations per lane), in precision TS.  The result is
+// written to x (double, LDS).
+template <typename TS>
+__device__ void pcr_solve(int n, const double* Td, const double* To, const double* rhs,
+                          double* x, PcrBuf<TS>& B) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    int j = lane + kWave * e;
+    if (j < n) {
+      B.a[0][j] = j > 0 ? (TS)To[j - 1] : (TS)0;
+      B.b[0][j] = (TS)Td[j];
+      B.c[0][j] = j < n - 1 ? (TS)To[j] : (TS)0;
+      B.d[0][j] = (TS)rhs[j];
+    }
+  }
+  wave_sync();
+  int cur = 0;
+  for (int s = 1; s < n; s <<= 1) {
+    TS na[2], nb[2], nc[2], nd[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      int j = lane + kWave * e;
+      if (j < n) {
+        TS aj = B.a[cur][j], bj = B.b[cur][j], cj = B.c[cur][j], dj = B.d[cur][j];
+        TS an = 0, cn = 0;
+        if (j - s >= 0) {
+          TS al = -aj / B.b[cur][j - s];
+          an = al * B.a[cur][j - s];
+          bj += al * B.c[cur][j - s];
+          dj += al * B.d[cur][j - s];
+        }
+        if (j + s < n) {
+          TS ga = -cj / B.b[cur][j + s];
+          cn = ga * B.c[cur][j + s];
+          bj += ga * B.a[cur][j + s];
+          dj += ga * B.d[cur][j + s];
+        }
+        na[e] = an; nb[e] = bj; nc[e] = cn; nd[e] = dj;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      int j = lane + kWave * e;
+      if (j < n) {
+        B.a[cur ^ 1][j] = na[e]; B.b[cur ^ 1][j] = nb[e];
+        B.c[cur ^ 1][j] = nc[e]; B.d[cur ^ 1][j] = nd[e];
+      }
+    }
+    wave_sync();
+    cur ^= 1;
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    int j = lane + kWave * e;
+    if (j < n) x[j] = (double)(B.d[cur][j] / B.b[cur][j]);
+  }
+  wave_sync();
+}
+
+struct SlabShared {
+  double S1[kMaxNt], S2[kMaxNt], Sd[kMaxNt], Sa2[kMaxNt], Sa[kMaxNt], Sad[kMaxNt];
+  double W[kMaxNt];      // W_k per slab
+  double lam[kMaxNt];    // current multipliers of the slab rows
+  double lamp[kMaxNt];   // Newton multipliers lam+
+  double Td[kMaxNt], To[kMaxNt], r[kMaxNt], res[kMaxNt], dx[kMaxNt];
+  double red[kSlabWaves][4];
+  double scal[16];
+  int flag[4];
+};
+
+// Row-k coefficient on slab k (derivative of row k w.r.t. u(x,k)).
+__device__ __forceinline__ double coef_a(bool f2, double c, double uu) {
+  return f2 ? (-1.0 - c * (1.0 - 2.0 * uu)) : 0.0;
+}
+
+template <int SPW, int XPL, bool UREG, typename TS>
+__global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  const int nx = D.nx, nt = D.nt, nr = nt - 1;
+  const bool f2 = (D.family == SNAP_FISHER_KPP);
+  const double c = f2 ? D.dt * D.p0 : 0.0;
+  const double wfloor = 0.1;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const bool bwd = A.backward != 0;
+
+  __shared__ SlabShared sh;
+  __shared__ PcrBuf<TS> pcr;
+
+  const double* uhat_g = A.uhat + D.var_off;
+  const double* aux = A.aux + D.aux_off;
+  const double m0 = f2 ? 0.0 : aux[nx];
+
+  double u[SPW][XPL];
+  double uh[UREG ? SPW : 1][UREG ? XPL : 1];
+  double gic[XPL], lamic[XPL], lampic[XPL];
+
+  auto slab_of = [&](int s) { return w + kSlabWaves * s; };
+  auto xof = [&](int j) { return lane + kWave * j; };
+  // u_hat as seen by the step: forward -> input u_hat; backward -> u* + grad_u,
+  // so that u - u_hat_eff = -grad_u and the step formula yields the adjoint.
+  auto uhat_at = [&](int s, int j) -> double {
+    if constexpr (UREG) {
+      return uh[s][j];
+    } else {
+      int64_t idx = (int64_t)slab_of(s) * nx + xof(j);
+      return bwd ? (A.u[D.var_off + idx] + A.grad_u[D.var_off + idx]) : uhat_g[idx];
+    }
+  };
+
+  // ---------------------------------------------------------------- load
+  double umax = 0.0;
+  bool nonfinite = false;
+#pragma unroll
+  for (int s = 0; s < SPW; ++s) {
+    const int k = slab_of(s);
+#pragma unroll
+    for (int j = 0; j < XPL; ++j) {
+      const int x = xof(j);
+      double uu = 0.0, hh = 0.0;
+      if (k < nt && x < nx) {
+        int64_t idx = (int64_t)k * nx + x;
+        if (bwd) {
+          uu = A.u[D.var_off + idx];
+          hh = uu + A.grad_u[D.var_off + idx];
+        } else {
+          hh = uhat_g[idx];
+          uu = hh;
+        }
+        umax = fmax(umax, fabs(hh));
+        nonfinite |= !finite(hh) || !finite(uu);
+      }
+      u[s][j] = uu;
+      if constexpr (UREG) uh[s][j] = hh;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < XPL; ++j) {
+    const int x = xof(j);
+    gic[j] = (w == 0 && x < nx) ? aux[x] : 0.0;
+    lamic[j] = (bwd && w == 0 && x < nx) ? A.lam[D.row_off + x] : 0.0;
+    lampic[j] = 0.0;
+  }
+  for (int k = threadIdx.x; k < kMaxNt; k += kSlabThreads) {
+    double l = (bwd && k < nr) ? A.lam[D.row_off + nx + k] : 0.0;
+    sh.lam[k] = l;
+    sh.lamp[k] = 0.0;
+    double wk = (k < nr) ? 1.0 + 2.0 * c * l : 1.0;
+    sh.W[k] = fmax(wk, wfloor);
+  }
+  {
+    double mx = wave_max(umax);
+    int nf = __any(nonfinite) ? 1 : 0;
+    if (lane == 0) { sh.red[w][0] = mx; sh.red[w][1] = (double)nf; }
+  }
+  __syncthreads();
+  double uscale = 0.0, nfin = 0.0;
+  for (int q = 0; q < kSlabWaves; ++q) { uscale = fmax(uscale, sh.red[q][0]); nfin += sh.red[q][1]; }
+  uscale += 1.0;
+  __syncthreads();
+
+  double mu = 0.0;
+  int iters = 0, backtracks = 0, refines = 0, status = SNAP_ST_MAX_ITER;
+  double hinf = 0.0, stinf = 0.0;
+  if (nfin > 0.0) status = SNAP_ST_NONFINITE;
+  const int max_it = bwd ? 1 : A.opt.max_newton;
+
+  for (int it = 0; status != SNAP_ST_NONFINITE; ++it) {
+    // ------------------------------------------------ pass 1: slab sums
+    double st_w = 0.0;
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      const int k = slab_of(s);
+      if (k >= nt) continue;                       // uniform over the wavefront
+      const double lk = (k < nr) ? sh.lam[k] : 0.0;
+      const double lkm = (k >= 1) ? sh.lam[k - 1] : 0.0;
+      double S1 = 0, S2 = 0, Sd = 0, Sa2 = 0, Sa = 0, Sad = 0;
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) {
+        const int x = xof(j);
+        if (x < nx) {
+          const double uu = u[s][j];
+          const double d = uu - uhat_at(s, j);
+          const double a = (k < nr) ? coef_a(f2, c, uu) : 0.0;
+          S1 += uu; S2 += uu * (1.0 - uu); Sd += d;
+          Sa2 += a * a; Sa += a; Sad += a * d;
+          double jt = d + a * lk + (k >= 1 ? lkm : 0.0) + (k == 0 ? lamic[j] : 0.0);
+          st_w = fmax(st_w, fabs(jt));
+        }
+      }
+      S1 = wave_sum(S1); S2 = wave_sum(S2); Sd = wave_sum(Sd);
+      Sa2 = wave_sum(Sa2); Sa = wave_sum(Sa); Sad = wave_sum(Sad);
+      if (lane == 0) {
+        sh.S1[k] = S1; sh.S2[k] = S2; sh.Sd[k] = Sd;
+        sh.Sa2[k] = Sa2; sh.Sa[k] = Sa; sh.Sad[k] = Sad;
+      }
+    }
+    // IC rows live on slab 0, owned by wavefront 0 (s = 0)
+    double ric[XPL];
+    if (w == 0) {
+      double sar = 0.0, hicmax = 0.0, hic1 = 0.0;
+      const double W0 = sh.W[0];
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) {
+        const int x = xof(j);
+        ric[j] = 0.0;
+        if (x < nx) {
+          const double uu = u[0][j];
+          const double d = uu - uhat_at(0, j);
+          const double hic = bwd ? 0.0 : uu - gic[j];
+          ric[j] = hic - d / W0;
+          const double a0 = (nr > 0) ? coef_a(f2, c, uu) : 0.0;
+          sar += a0 * ric[j];
+          hicmax = fmax(hicmax, fabs(hic));
+          hic1 += fabs(hic);
+        }
+      }
+      sar = wave_sum(sar); hicmax = wave_max(hicmax); hic1 = wave_sum(hic1);
+      if (lane == 0) { sh.scal[0] = sar; sh.scal[1] = hicmax; sh.scal[2] = hic1; }
+    }
+    st_w = wave_max(st_w);
+    if (lane == 0) sh.red[w][0] = st_w;
+    __syncthreads();
+
+    // ------------------------------------------------ wavefront 0: rows, test, solve
+    if (w == 0) {
+      double hmax = sh.scal[1], h1 = sh.scal[2];
+      for (int k = lane; k < nr; k += kWave) {
+        double hk = bwd ? 0.0
+                        : (f2 ? sh.S1[k + 1] - sh.S1[k] - c * sh.S2[k] : sh.S1[k + 1] - m0);
+        const double Wk = sh.W[k], Wk1 = sh.W[k + 1];
+        double rk = hk - (sh.Sad[k] / Wk + sh.Sd[k + 1] / Wk1);
+        if (k == 0) rk -= sh.scal[0];
+        sh.r[k] = rk;
+        sh.Td[k] = (k == 0 ? 0.0 : sh.Sa2[k] / Wk) + (double)nx / Wk1;
+        sh.To[k] = (k + 1 < nr) ? sh.Sa[k + 1] / Wk1 : 0.0;
+        hmax = fmax(hmax, fabs(hk));
+        h1 += fabs(hk);
+        if (!finite(hk)) hmax = __builtin_nan("");
+      }
+      hmax = wave_max(hmax);
+      h1 = wave_sum(h1);
+      double stmax = 0.0;
+      for (int q = 0; q < kSlabWaves; ++q) stmax = fmax(stmax, sh.red[q][0]);
+      int done = 0;
+      if (!bwd) {
+        hinf = hmax; stinf = stmax;
+        if (!finite(hmax) || !finite(stmax)) done = 2;
+        else if (hmax <= A.opt.tol_h && stmax <= A.opt.tol_s * uscale) done = 1;
+        else if (it >= max_it) done = 3;
+      }
+      if (lane == 0) { sh.flag[0] = done; sh.scal[3] = h1; }
+      if (!done && nr > 0) {
+        if constexpr (sizeof(TS) == sizeof(double)) {
+          pcr_solve<TS>(nr, sh.Td, sh.To, sh.r, sh.lamp, pcr);
+        } else {
+          // float32 solve + float64 residual refinement
+          pcr_solve<TS>(nr, sh.Td, sh.To, sh.r, sh.lamp, pcr);
+          double rn = 0.0;
+          for (int k = lane; k < nr; k += kWave) rn = fmax(rn, fabs(sh.r[k]));
+          rn = wave_max(rn);
+          for (int ref = 0; ref < 4; ++ref) {
+            double resmax = 0.0;
+            for (int k = lane; k < nr; k += kWave) {
+              double tx = sh.Td[k] * sh.lamp[k];
+              if (k > 0) tx += sh.To[k - 1] * sh.lamp[k - 1];
+              if (k + 1 < nr) tx += sh.To[k] * sh.lamp[k + 1];
+              sh.res[k] = sh.r[k] - tx;
+              resmax = fmax(resmax, fabs(sh.res[k]));
+            }
+            resmax = wave_max(resmax);
+            wave_sync();
+            if (!(resmax > 1e-15 * rn)) break;
+            pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
+            for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.dx[k];
+            wave_sync();
+            ++refines;
+          }
+        }
+      }
+      if (!done) {
+        const double l0 = nr > 0 ? sh.lamp[0] : 0.0;
+        const double W0 = sh.W[0];
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) {
+          const double a0 = (nr > 0) ? coef_a(f2, c, u[0][j]) : 0.0;
+          lampic[j] = W0 * ric[j] - a0 * l0;
+        }
+      }
+    }
+    __syncthreads();
+    const int done = sh.flag[0];
+    if (done) {
+      status = done == 1 ? SNAP_ST_CONVERGED : (done == 2 ? SNAP_ST_NONFINITE : SNAP_ST_MAX_ITER);
+      break;
+    }
+
+    // ------------------------------------------------ step p = -(d + J^T lam+)/W
+    // backward: the step is the adjoint; write it and stop
+    auto step_at = [&](int s, int j, int k, double uu) -> double {
+      const double d = uu - uhat_at(s, j);
+      const double a = (k < nr) ? coef_a(f2, c, uu) : 0.0;
+      double jt = d + a * ((k < nr) ? sh.lamp[k] : 0.0) + (k >= 1 ? sh.lamp[k - 1] : 0.0)
+                + (k == 0 ? lampic[j] : 0.0);
+      return -jt / sh.W[k];
+    };
+    if (bwd) {
+#pragma unroll
+      for (int s = 0; s < SPW; ++s) {
+        const int k = slab_of(s);
+        if (k >= nt) continue;
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) {
+          const int x = xof(j);
+          if (x < nx) A.grad_uhat[D.var_off + (int64_t)k * nx + x] = step_at(s, j, k, u[s][j]);
+        }
+      }
+      status = SNAP_ST_CONVERGED;
+      break;
+    }
+
+    // merit phi = 1/2||u - u_hat||^2 + mu*||h||_1 and its directional derivative
+    double lmax = 0.0;
+    for (int k = 0; k < nr; ++k) lmax = fmax(lmax, fabs(sh.lamp[k]));
+    if (w == 0) {
+      double lm = 0.0;
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) lm = fmax(lm, fabs(lampic[j]));
+      lm = wave_max(lm);
+      if (lane == 0) sh.scal[4] = lm;
+    }
+    {
+      double f0 = 0.0, dd = 0.0;
+#pragma unroll
+      for (int s = 0; s < SPW; ++s) {
+        const int k = slab_of(s);
+        if (k >= nt) continue;
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) {
+          if (xof(j) < nx) {
+            const double d = u[s][j] - uhat_at(s, j);
+            f0 += 0.5 * d * d;
+            dd += d * step_at(s, j, k, u[s][j]);
+          }
+        }
+      }
+      f0 = wave_sum(f0); dd = wave_sum(dd);
+      if (lane == 0) { sh.red[w][1] = f0; sh.red[w][2] = dd; }
+    }
+    __syncthreads();
+    lmax = fmax(lmax, sh.scal[4]);
+    mu = fmax(mu, 1.1 * lmax + 1e-8);
+    double phi0 = 0.0, dphi = 0.0;
+    for (int q = 0; q < kSlabWaves; ++q) { phi0 += sh.red[q][1]; dphi += sh.red[q][2]; }
+    const double h1_0 = sh.scal[3];
+    phi0 += mu * h1_0;
+    dphi -= mu * h1_0;
+    __syncthreads();
+
+    // ------------------------------------------------ backtracking line search
+    double alpha = 1.0;
+    int accepted = 0;
+    for (int ls = 0; ls <= A.opt.max_ls; ++ls) {
+      double ft = 0.0;
+#pragma unroll
+      for (int s = 0; s < SPW; ++s) {
+        const int k = slab_of(s);
+        if (k >= nt) continue;
+        double S1 = 0, S2 = 0;
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) {
+          if (xof(j) < nx) {
+            const double ut = u[s][j] + alpha * step_at(s, j, k, u[s][j]);
+            const double d = ut - uhat_at(s, j);
+            ft += 0.5 * d * d;
+            S1 += ut; S2 += ut * (1.0 - ut);
+          }
+        }
+        S1 = wave_sum(S1); S2 = wave_sum(S2);
+        if (lane == 0) { sh.S1[k] = S1; sh.S2[k] = S2; }
+      }
+      if (w == 0) {
+        double hic1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) {
+          if (xof(j) < nx) {
+            const double ut = u[0][j] + alpha * step_at(0, j, 0, u[0][j]);
+            hic1 += fabs(ut - gic[j]);
+          }
+        }
+        hic1 = wave_sum(hic1);
+        if (lane == 0) sh.scal[5] = hic1;
+      }
+      ft = wave_sum(ft);
+      if (lane == 0) sh.red[w][3] = ft;
+      __syncthreads();
+      if (w == 0) {
+        double h1 = sh.scal[5];
+        for (int k = lane; k < nr; k += kWave) {
+          double hk = f2 ? sh.S1[k + 1] - sh.S1[k] - c * sh.S2[k] : sh.S1[k + 1] - m0;
+          h1 += fabs(hk);
+        }
+        h1 = wave_sum(h1);
+        double phi = mu * h1;
+        for (int q = 0; q < kSlabWaves; ++q) phi += sh.red[q][3];
+        // roundoff allowance: near the solution phi differences sit at the
+        // rounding level of phi itself
+        const double slack = 1e-13 * fabs(phi0);
+        int ok = (phi <= phi0 + 1e-4 * alpha * dphi + slack) || !(dphi < 0.0) ? 1 : 0;
+        if (lane == 0) sh.flag[1] = ok;
+      }
+      __syncthreads();
+      if (sh.flag[1]) { accepted = 1; break; }
+      alpha *= 0.5;
+      ++backtracks;
+    }
+    if (!accepted) {
+      status = SNAP_ST_LS_FAIL;
+      break;
+    }
+    // ------------------------------------------------ accept: u += alpha p, lam += alpha (lam+ - lam)
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      const int k = slab_of(s);
+      if (k >= nt) continue;
+#pragma unroll
+      for (int j = 0; j < XPL; ++j)
+        if (xof(j) < nx) u[s][j] += alpha * step_at(s, j, k, u[s][j]);
+    }
+    // every thread computed its step with the old u above; now update lam, W
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) lamic[j] += alpha * (lampic[j] - lamic[j]);
+    }
+    for (int k = threadIdx.x; k < nr; k += kSlabThreads) {
+      double l = sh.lam[k] + alpha * (sh.lamp[k] - sh.lam[k]);
+      sh.lam[k] = l;
+      sh.W[k] = fmax(1.0 + 2.0 * c * l, wfloor);
+    }
+    ++iters;
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------------- outputs
+  if (!bwd) {
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      const int k = slab_of(s);
+      if (k >= nt) continue;
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) {
+        const int x = xof(j);
+        if (x < nx) A.u[D.var_off + (int64_t)k * nx + x] = u[s][j];
+      }
+    }
+    if (w == 0) {
+#pragma unroll
+      for (int j = 0; j < XPL; ++j)
+        if (xof(j) < nx) A.lam[D.row_off + xof(j)] = lamic[j];
+    }
+    for (int k = threadIdx.x; k < nr; k += kSlabThreads) A.lam[D.row_off + nx + k] = sh.lam[k];
+  }
+  if (threadIdx.x == 0) {
+    snap_sample_stats st;
+    st.status = status;
+    st.newton_iters = iters;
+    st.ls_backtracks = backtracks;
+    st.refine_steps = refines;
+    st.h_inf = bwd ? 0.0 : hinf;
+    st.stat_inf = bwd ? 0.0 : stinf;
+    A.stats[sid] = st;
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+using SlabLaunch = void (*)(const KernelArgs&, hipStream_t);
+
+template <int SPW, int XPL, typename TS>
+static void launch_slab(const KernelArgs& a, hipStream_t st) {
+  constexpr bool ureg = SPW * XPL <= 32;
+  hipLaunchKernelGGL((slab_kernel<SPW, XPL, ureg, TS>), dim3(a.count), dim3(kSlabThreads), 0, st, a);
+}
+
+template <typename TS>
+static SlabLaunch pick_slab(int spw, int xpl) {
+#define SNAP_SLAB_CASE(S, X) if (spw <= S && xpl == X) return &launch_slab<S, X, TS>;
+#define SNAP_SLAB_ROW(X) SNAP_SLAB_CASE(2, X) SNAP_SLAB_CASE(4, X) SNAP_SLAB_CASE(8, X) \
+                         SNAP_SLAB_CASE(13, X) SNAP_SLAB_CASE(16, X)
+  SNAP_SLAB_ROW(1) SNAP_SLAB_ROW(2) SNAP_SLAB_ROW(3) SNAP_SLAB_ROW(4)
+#undef SNAP_SLAB_ROW
+#undef SNAP_SLAB_CASE
+  return nullptr;
+}
+
+// Host entry used by the plan: launch one workgroup per listed sample, all of
+// which share (nx, nt) class (spw, xpl).
+int slab_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st) {
+  if (a.count == 0) return 0;
+  if (nt < 1 || nt > kMaxNt || nx < 1 || nx > 4 * kWave) return SNAP_EUNSUPPORTED;
+  const int spw = (nt + kSlabWaves - 1) / kSlabWaves;
+  const int xpl = (nx + kWave - 1) / kWave;
+  SlabLaunch f = mixed ? pick_slab<float>(spw, xpl) : pick_slab<double>(spw, xpl);
+  if (!f) return SNAP_EUNSUPPORTED;
+  f(a, st);
+  return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP;
+}
+
+bool slab_supported(int nx, int nt) {
+  return nt >= 1 && nt <= kMaxNt && nx >= 1 && nx <= 4 * kWave;
+}
+
+}  // namespace snap

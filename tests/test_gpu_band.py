@@ -1,0 +1,74 @@
+"""GPU parity of the banded Burgers path (block-band LDL^T Schur solver) against the oracle."""
+import numpy as np
+import pytest
+
+import synthgen
+from oracle.families import family_of
+from oracle.kkt import adjoint_sample, project_sample
+from oracle.metric import max_violation
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2607_00095_amd as snap  # noqa: E402
+from gpu_helpers import gpu_backward, gpu_project, rel_err  # noqa: E402
+
+H_TOL = 1e-8
+
+
+def _check(batch, res, indices, u_tol, lam_tol):
+    st = res["stats"]
+    assert (st["status"][indices] == 0).all(), st[indices]
+    hv = max_violation(batch, res["u_np"], indices=indices)
+    assert hv[indices].max() <= H_TOL, hv[indices].max()
+    worst = 0.0
+    for s in indices:
+        smp = batch.samples[s]
+        u_o, lam_o = project_sample(family_of(smp), smp.uhat.reshape(-1))
+        vo, ro = batch.var_off[s], batch.row_off[s]
+        e = rel_err(res["u_np"][vo:vo + smp.n], u_o)
+        worst = max(worst, e)
+        assert e <= u_tol, (s, e)
+        lam_g = res["lam_np"][ro:ro + smp.m]
+        assert np.abs(lam_g - lam_o).max() <= lam_tol * (1 + np.abs(lam_o).max()), s
+    return worst
+
+
+@pytest.mark.parametrize("nx,nt", [(16, 8), (13, 6), (32, 17), (3, 4), (40, 2)])
+def test_burgers_small_fp64(nx, nt):
+    b = synthgen.burgers_batch(batch=3, nx=nx, nt=nt, seed=nx * 31 + nt)
+    res = gpu_project(b)
+    _check(b, res, list(range(len(b))), 1e-10, 1e-8)
+
+
+@pytest.mark.parametrize("nx,nt", [(64, 32), (128, 16)])
+def test_burgers_medium_fp64(nx, nt):
+    b = synthgen.burgers_batch(batch=2, nx=nx, nt=nt, seed=nx + nt)
+    res = gpu_project(b)
+    _check(b, res, [0, 1], 1e-10, 1e-8)
+
+
+@pytest.mark.parametrize("nx,nt", [(16, 8), (64, 32)])
+def test_burgers_mixed(nx, nt):
+    b = synthgen.burgers_batch(batch=2, nx=nx, nt=nt, seed=5 * nx + nt)
+    res = gpu_project(b, snap.Options(precision=snap.PREC_MIXED))
+    _check(b, res, [0, 1], 1e-6, 1e-4)
+
+
+@pytest.mark.parametrize("prec", [snap.PREC_FP64, snap.PREC_MIXED])
+def test_burgers_backward(prec):
+    b = synthgen.burgers_batch(batch=2, nx=16, nt=8, seed=77)
+    for flags in (0, snap.FLAG_KEEP_FACTOR):
+        res = gpu_project(b, snap.Options(precision=prec, flags=flags))
+        grad = synthgen.upstream_grad(b, seed=5)
+        g, st = gpu_backward(res, grad)
+        assert (st["status"] == 0).all()
+        for s, smp in enumerate(b.samples):
+            vo = b.var_off[s]
+            u_o, lam_o = project_sample(family_of(smp), smp.uhat.reshape(-1))
+            g_o = adjoint_sample(family_of(smp), u_o, lam_o, grad[vo:vo + smp.n])
+            tol = 1e-10 if prec == snap.PREC_FP64 else 1e-6
+            assert rel_err(g[vo:vo + smp.n], g_o) <= tol, (flags, s, rel_err(g[vo:vo + smp.n], g_o))

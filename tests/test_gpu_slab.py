@@ -1,0 +1,107 @@
+"""GPU parity of the slab-row families (mass + IC, Fisher-KPP) against the oracle."""
+import numpy as np
+import pytest
+
+import synthgen
+from oracle.families import family_of
+from oracle.kkt import adjoint_sample, project_sample
+from oracle.metric import max_violation
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2607_00095_amd as snap  # noqa: E402
+from gpu_helpers import gpu_backward, gpu_project, rel_err  # noqa: E402
+
+U_TOL_FP64 = 1e-10
+U_TOL_MIXED = 1e-6
+H_TOL = 1e-8
+
+
+def _check_against_oracle(batch, res, indices, u_tol, lam_tol):
+    assert (res["stats"]["status"][indices] == 0).all(), res["stats"][indices]
+    hv = max_violation(batch, res["u_np"], indices=indices)
+    assert hv[indices].max() <= H_TOL
+    for s in indices:
+        smp = batch.samples[s]
+        u_o, lam_o = project_sample(family_of(smp), smp.uhat.reshape(-1))
+        vo, ro = batch.var_off[s], batch.row_off[s]
+        u_g = res["u_np"][vo:vo + smp.n]
+        lam_g = res["lam_np"][ro:ro + smp.m]
+        assert rel_err(u_g, u_o) <= u_tol, (s, rel_err(u_g, u_o))
+        assert np.abs(lam_g - lam_o).max() <= lam_tol * (1 + np.abs(lam_o).max()), s
+
+
+@pytest.mark.parametrize("nx,nt", [(64, 32), (13, 5), (96, 33), (200, 100), (256, 128), (7, 1)])
+def test_mass_ic_matches_oracle(nx, nt):
+    b = synthgen.mass_ic_batch(batch=4, nx=nx, nt=nt, seed=nx * 7 + nt)
+    res = gpu_project(b)
+    _check_against_oracle(b, res, range(len(b)), U_TOL_FP64, 1e-8)
+
+
+def test_mass_ic_full_config():
+    b = synthgen.make("mass_ic")
+    res = gpu_project(b)
+    _check_against_oracle(b, res, range(len(b)), U_TOL_FP64, 1e-8)
+
+
+@pytest.mark.parametrize("nx,nt", [(32, 20), (128, 100), (70, 9), (192, 128), (256, 64), (5, 2)])
+def test_fisher_kpp_matches_oracle(nx, nt):
+    b = synthgen.fisher_kpp_batch(batch=3, nx=nx, nt=nt, seed=nx + nt)
+    res = gpu_project(b)
+    _check_against_oracle(b, res, range(len(b)), U_TOL_FP64, 1e-8)
+
+
+def test_fisher_kpp_full_config_sampled():
+    b = synthgen.make("fisher_kpp")
+    res = gpu_project(b)
+    assert (res["stats"]["status"] == 0).all()
+    assert res["stats"]["h_inf"].max() <= H_TOL
+    _check_against_oracle(b, res, [0, 1, 97, 128, 200, 255], U_TOL_FP64, 1e-8)
+
+
+def test_fisher_kpp_mixed_precision():
+    b = synthgen.fisher_kpp_batch(batch=16, nx=128, nt=100, seed=2001)
+    res = gpu_project(b, snap.Options(precision=snap.PREC_MIXED))
+    _check_against_oracle(b, res, [0, 5, 15], U_TOL_MIXED, 1e-4)
+    ref = gpu_project(b)
+    assert rel_err(res["u_np"], ref["u_np"]) <= U_TOL_MIXED
+
+
+def test_empty_batch():
+    b = synthgen.Batch([]) if False else None
+    plan = snap.Plan([], [], [], [])
+    assert plan.total_vars == 0
+    u, lam, st, ws = snap.project(plan, torch.zeros(1, dtype=torch.float64, device="cuda"), None)
+
+
+@pytest.mark.parametrize("name,kw", [("mass_ic", dict(batch=3, nx=20, nt=6)),
+                                     ("fisher_kpp", dict(batch=3, nx=48, nt=12))])
+def test_backward_matches_oracle_adjoint(name, kw):
+    b = synthgen.make(name, **kw)
+    res = gpu_project(b)
+    grad = synthgen.upstream_grad(b, seed=3)
+    g_gpu, st = gpu_backward(res, grad)
+    for s, smp in enumerate(b.samples):
+        vo, ro = b.var_off[s], b.row_off[s]
+        u_o, lam_o = project_sample(family_of(smp), smp.uhat.reshape(-1))
+        g_o = adjoint_sample(family_of(smp), u_o, lam_o, grad[vo:vo + smp.n])
+        assert rel_err(g_gpu[vo:vo + smp.n], g_o) <= 1e-10
+
+
+def test_nonfinite_input_is_reported():
+    b = synthgen.fisher_kpp_batch(batch=2, nx=16, nt=4, seed=1)
+    b.uhat[b.var_off[1] + 5] = np.nan
+    res = gpu_project(b)
+    assert res["stats"]["status"][0] == 0
+    assert snap.status_name(res["stats"]["status"][1]) == "nonfinite"
+
+
+def test_max_newton_one_reports_max_iter():
+    b = synthgen.fisher_kpp_batch(batch=2, nx=32, nt=10, seed=2)
+    res = gpu_project(b, snap.Options(max_newton=1))
+    assert (res["stats"]["status"] == 1).all()
+    assert (res["stats"]["newton_iters"] == 1).all()
