@@ -1,0 +1,246 @@
+"""Benchmark of the batched constraint projection on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one forward projection (the whole Newton/SQP hot path: stencil
+evaluation, Schur assembly, factorization, solves, line search, convergence
+test) of one batch of synthetic samples already resident in HBM.  The default
+workload is the Fisher-KPP nonlinear mass-law batch (256 samples, 128 x 100
+grid, FP64).  The same run also times the mixed-precision forward and the
+adjoint, measures the dominant kernel against the HBM roofline with HIP events
+on the launch stream, and times the CPU oracle on a bounded sample of the same
+workload.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synthgen  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+H_FEAS = 1e-8
+
+# bytes that one sample must move at minimum: read u_hat and aux, write u,
+# lambda and the stats record (float64 everywhere, 32-byte stats)
+def algorithmic_bytes(batch):
+    tot = 0
+    for s in batch.samples:
+        tot += 8 * (2 * s.n + s.m + len(s.aux)) + 32
+    return tot
+
+
+KERNEL_SOURCES = {
+    "fisher_kpp": "paper_2607_00095_amd/csrc/snap_slab.hip",
+    "mass_ic": "paper_2607_00095_amd/csrc/snap_slab.hip",
+    "burgers_lf": "paper_2607_00095_amd/csrc/snap_band.hip",
+    "ragged": "paper_2607_00095_amd/csrc/snap_band.hip",
+}
+KERNEL_NAMES = {
+    "fisher_kpp": "slab_kernel", "mass_ic": "slab_kernel",
+    "burgers_lf": "band_kernel", "ragged": "band_kernel",
+}
+
+
+def source_hash(path):
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("source_sha") != source_hash(KERNEL_SOURCES[workload]):
+        return None
+    return t.get("bytes_per_launch")
+
+
+# ------------------------------------------------------------------ CPU oracle
+def _oracle_one(args):
+    name, kw, idx = args
+    from oracle.families import family_of
+    from oracle.kkt import project_sample
+    b = synthgen.make(name, **kw)
+    s = b.samples[idx]
+    u, lam = project_sample(family_of(s), s.uhat.reshape(-1))
+    return idx, u
+
+
+def cpu_baseline(name, kw, batch, budget_s=15.0):
+    from oracle.families import family_of
+    from oracle.kkt import project_sample
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    s0 = batch.samples[0]
+    project_sample(family_of(s0), s0.uhat.reshape(-1))
+    t1 = max(time.perf_counter() - t0, 1e-3)
+    count = int(np.clip(budget_s * workers / t1, workers, len(batch)))
+    idx = list(range(count))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_one, [(name, kw, i) for i in idx], chunksize=1)
+    wall = time.perf_counter() - t0
+    return dict(value=count / wall, unit="samples/s", cores=workers, kind="oracle",
+                sample=f"first {count} of {len(batch)} samples of the same batch, "
+                       f"process pool of {workers}, {wall:.1f} s wall"), dict(res)
+
+
+# ------------------------------------------------------------------ GPU timing
+def time_calls(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3 / steps   # seconds per call
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fisher_kpp", choices=sorted(KERNEL_SOURCES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forward-only", action="store_true",
+                    help="time the FP64 forward only (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: every sample is independent and the library has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2607_00095_amd as snap
+
+    name = args.workload
+    spec = dict(synthgen.CONFIGS[name]["kw"])
+    batch = synthgen.make(name)
+    B = len(batch)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    uhat = torch.from_numpy(batch.uhat).to(dev)
+    aux = torch.from_numpy(batch.aux).to(dev)
+
+    plan64 = snap.Plan.from_batch(batch, snap.Options())
+    ws = plan64.new_workspace()
+    u = torch.empty(plan64.total_vars, dtype=torch.float64, device=dev)
+    lam = torch.empty(max(plan64.total_rows, 1), dtype=torch.float64, device=dev)
+    st = torch.empty(B * 32, dtype=torch.uint8, device=dev)
+
+    def fwd64():
+        snap.project(plan64, uhat, aux, ws, u, lam, st, stream)
+
+    # timed region: K forward projections of the resident batch
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        fwd64()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        fwd64()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sec64 = ev0.elapsed_time(ev1) / 1e3 / args.steps
+
+    stats = snap.stats_to_numpy(st, B)
+    u_np = u.cpu().numpy()
+    from oracle.metric import max_violation   # feasibility re-evaluated by the oracle's h
+    hv = max_violation(batch, u_np)
+    ok = (stats["status"] == 0) & (hv <= H_FEAS)
+    projected = int(ok.sum())
+    value = projected / sec64
+
+    out = {
+        "metric": "projected samples/sec at ||h||inf<=1e-8 (forward projection, plain FP64)",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "batch": B, **{k: v for k, v in spec.items() if k != "seed"},
+                   "seed": spec.get("seed"), "precision": "fp64"},
+        "projected": projected,
+        "max_h_inf": float(hv.max()),
+        "newton_iters_mean": float(stats["newton_iters"].mean()),
+    }
+
+    if not args.forward_only:
+        # mixed precision forward
+        plan32 = snap.Plan.from_batch(batch, snap.Options(precision=snap.PREC_MIXED))
+        ws32 = plan32.new_workspace()
+        u32 = torch.empty_like(u)
+        st32 = torch.empty_like(st)
+        sec32 = time_calls(lambda: snap.project(plan32, uhat, aux, ws32, u32, lam, st32, stream),
+                           args.steps, args.warmup, stream)
+        s32 = snap.stats_to_numpy(st32, B)
+        u32_np = u32.cpu().numpy()
+        hv32 = max_violation(batch, u32_np)
+        ok32 = (s32["status"] == 0) & (hv32 <= H_FEAS)
+        out["mixed"] = {"value": int(ok32.sum()) / sec32, "ms_per_step": sec32 * 1e3,
+                        "max_rel_u_vs_fp64": float(np.max([
+                            np.linalg.norm(u32_np[o:o + s.n] - u_np[o:o + s.n]) /
+                            max(np.linalg.norm(u_np[o:o + s.n]), 1e-300)
+                            for s, o in zip(batch.samples, batch.var_off)]))}
+        # adjoint (vector-Jacobian product) with the factor kept by the forward
+        plank = snap.Plan.from_batch(batch, snap.Options(flags=snap.FLAG_KEEP_FACTOR))
+        wsk = plank.new_workspace()
+        uk, lk, stk = torch.empty_like(u), torch.empty_like(lam), torch.empty_like(st)
+        snap.project(plank, uhat, aux, wsk, uk, lk, stk, stream)
+        grad = torch.from_numpy(synthgen.upstream_grad(batch, seed=7)).to(dev)
+        gout = torch.empty_like(u)
+        stb = torch.empty_like(st)
+        secb = time_calls(lambda: snap.project_backward(plank, uk, lk, aux, wsk, grad, gout, stb, stream),
+                          args.steps, args.warmup, stream)
+        out["backward"] = {"value": B / secb, "ms_per_step": secb * 1e3, "unit": "samples/s"}
+
+    # roofline of the dominant kernel: the forward launch is one kernel per
+    # family group; events on the launch stream bracket it
+    abytes = algorithmic_bytes(batch)
+    achieved = abytes / sec64 / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name),
+                       "kernel": KERNEL_NAMES[name], "algorithmic_bytes_per_launch": abytes}
+
+    if not args.no_cpu_baseline:
+        cb, orc = cpu_baseline(name, spec, batch)
+        out["cpu_baseline"] = cb
+        errs = []
+        for i, uo in orc.items():
+            o, n = batch.var_off[i], batch.samples[i].n
+            errs.append(np.linalg.norm(u_np[o:o + n] - uo) / max(np.linalg.norm(uo), 1e-300))
+        out["parity"] = {"max_rel_u_vs_oracle": float(max(errs)), "samples": len(errs)}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

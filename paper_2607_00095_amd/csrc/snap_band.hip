@@ -36,17 +36,22 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 
 template <typename R> struct Mfma;
+// Operand layouts (both types): A[i][k] in lane i + 16k, B[k][j] in lane j + 16k.
+// Result layout differs: element e of lane (j + 16g) holds row g + 4e (f64) or
+// row 4g + e (f32), column j (checked on gfx950 by an in-bounds probe).
 template <> struct Mfma<double> {
   using V = dvec4;
   static __device__ __forceinline__ V mma(double a, double b, V c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int g, int e) { return g + 4 * e; }
 };
 template <> struct Mfma<float> {
   using V = fvec4;
   static __device__ __forceinline__ V mma(float a, float b, V c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int g, int e) { return 4 * g + e; }
 };
 
 constexpr int kT = 16;              // block size
@@ -124,6 +129,16 @@ __host__ __device__ inline WsLayout ws_layout(int nx, int nt, int BB, size_t rsi
 // d(v) = u - u_hat (forward), -g (backward)
 __device__ __forceinline__ double dres(const Ctx& C, int v) {
   return C.bwd ? -C.g[v] : C.u[v] - C.uh[v];
+}
+
+__device__ __forceinline__ double jt_at(const Ctx& C, const double* y, int k, int x);
+
+// residual entering the Schur right-hand side: the stationarity residual
+// u - u_hat + J^T lam (forward; the system is solved for the multiplier
+// increment, whose right-hand side vanishes at the solution), or -g (adjoint)
+__device__ __forceinline__ double gres(const Ctx& C, int k, int x) {
+  const int v = k * C.nx + x;
+  return C.bwd ? -C.g[v] : C.u[v] - C.uh[v] + jt_at(C, C.lam, k, x);
 }
 
 // W at variable (k, x) from the current multipliers
@@ -231,7 +246,7 @@ __device__ void assemble_row(const Ctx& C, int r, int a, int I, R (*NR)[kTL], do
     const double uy = C.u[v];
     const double al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
     const double s = al / w_at(C, kk, y);
-    rhs -= s * dres(C, (int)v);
+    rhs -= s * gres(C, kk, y);
     // rows touching variable (kk, y): (kk-1, y) with 1; (kk, y-1), (kk, y), (kk, y+1)
     if (kk >= 1) scatter_s<BB, R>(C, I, a, lo, hi, NR, kk - 1, y, s);
     if (kk <= C.nt - 2) {
@@ -297,7 +312,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
   auto load_nr = [&](int s, int d) {
     V v;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = sh.NR[d][(4 * lk + e) * kLd + li];
+    for (int e = 0; e < 4; ++e) v[e] = sh.NR[d][Mfma<R>::row(lk, e) * kLd + li];
     acc[s] = v;
   };
 
@@ -325,7 +340,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       if (sd[s] < 0) continue;
       if (slot_row(s, J) - sd[s] == J) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sh.P[sd[s]][(4 * lk + e) * kLd + li] = acc[s][e];
+        for (int e = 0; e < 4; ++e) sh.P[sd[s]][Mfma<R>::row(lk, e) * kLd + li] = acc[s][e];
       }
     }
     zero_nr();
@@ -416,8 +431,8 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       R* Lgd = Lg + ((size_t)J * (BB + 1) + d) * 256;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        sh.P[d][(4 * lk + e) * kLd + li] = res[e];
-        Lgd[(4 * lk + e) * kT + li] = res[e];
+        sh.P[d][Mfma<R>::row(lk, e) * kLd + li] = res[e];
+        Lgd[Mfma<R>::row(lk, e) * kT + li] = res[e];
       }
     }
     __syncthreads();
@@ -713,11 +728,10 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2
 
   for (int it = 0; status != SNAP_ST_NONFINITE; ++it) {
     // ---- evaluate h, stationarity and the objective at (u, lam)
-    double hm = 0.0, h1 = 0.0, sm = 0.0, f0 = 0.0;
+    double hm = 0.0, h1 = 0.0, sm = 0.0;
     for (int v = threadIdx.x; v < C.n; v += NT) {
       const int k = v / C.nx, x = v - k * C.nx;
       const double d = dres(C, v);
-      f0 += 0.5 * d * d;
       sm = fmax(sm, fabs(d + jt_at(C, C.lam, k, x)));
       if (k <= C.nt - 2) {
         const double h = h_row(C, k, x);
@@ -729,7 +743,6 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2
     hm = block_max<NW>(hm, sh.red, 0);
     sm = block_max<NW>(sm, sh.red, 1);
     h1 = block_sum<NW>(h1, sh.red, 2);
-    f0 = block_sum<NW>(f0, sh.red, 3);
     hinf = hm; stinf = sm;
     if (!finite(hm) || !finite(sm)) { status = SNAP_ST_NONFINITE; break; }
     const bool conv = hm <= A.opt.tol_h && sm <= A.opt.tol_s * uscale;
@@ -746,21 +759,27 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2
     if (bad) { status = SNAP_ST_SINGULAR_PIVOT; break; }
     refines += solve_with_factor<BB, NW, R>(C, WL, sh, true, lamp);
     __syncthreads();
+    for (int r = threadIdx.x; r < C.m; r += NT) lamp[r] += C.lam[r];   // lam+ = lam + dlam
+    __syncthreads();
 
     // ---- step p = -W^{-1}(d + J^T lam+), merit derivative
-    double dd = 0.0, lmax = 0.0;
+    double dd = 0.0, pp = 0.0, lmax = 0.0;
     for (int v = threadIdx.x; v < C.n; v += NT) {
       const int k = v / C.nx, x = v - k * C.nx;
       const double d = dres(C, v);
       const double p = -(d + jt_at(C, lamp, k, x)) / w_at(C, k, x);
       pv[v] = p;
       dd += d * p;
+      pp += p * p;
     }
     for (int r = threadIdx.x; r < C.m; r += NT) lmax = fmax(lmax, fabs(lamp[r]));
     dd = block_sum<NW>(dd, sh.red, 0);
+    pp = block_sum<NW>(pp, sh.red, 2);
     lmax = block_max<NW>(lmax, sh.red, 1);
     mu = fmax(mu, 1.1 * lmax + 1e-8);
-    const double phi0 = f0 + mu * h1;
+    // merit phi = 1/2||u - u_hat||^2 + mu ||h||_1; its change along p is formed
+    // from differences (alpha d.p + alpha^2/2 p.p + mu (||h_t||_1 - ||h||_1)),
+    // never from phi values themselves, so rounding of the large sums cancels
     const double dphi = dd - mu * h1;
 
     // ---- backtracking on the l1 merit; trial points are evaluated without
@@ -768,11 +787,9 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2
     double alpha = 1.0;
     int ok = 0;
     for (int ls = 0; ls <= A.opt.max_ls; ++ls) {
-      double ft = 0.0, ht = 0.0;
+      double ht = 0.0;
       for (int v = threadIdx.x; v < C.n; v += NT) {
         const int k = v / C.nx, x = v - k * C.nx;
-        const double dt_ = dres(C, v) + alpha * pv[v];
-        ft += 0.5 * dt_ * dt_;
         if (k <= C.nt - 2) {
           const size_t b0 = (size_t)k * C.nx;
           const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
@@ -784,10 +801,11 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2
           ht += fabs(h);
         }
       }
-      ft = block_sum<NW>(ft, sh.red, 0);
       ht = block_sum<NW>(ht, sh.red, 1);
-      const double phi = ft + mu * ht;
-      if (phi <= phi0 + 1e-4 * alpha * dphi + 1e-13 * fabs(phi0) || !(dphi < 0.0)) { ok = 1; break; }
+      const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (ht - h1);
+      // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
+      // ||h||_1 along p sits below the rounding of the row sums
+      if (dphi_t <= 1e-4 * alpha * dphi || !(dphi < 0.0) || hinf <= 1e-6) { ok = 1; break; }
       alpha *= 0.5;
       ++backtracks;
     }
