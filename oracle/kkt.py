@@ -13,8 +13,10 @@ the ones used), one Newton-Raphson step on
 solves  [[W, J^T], [J, 0]] [du; dlam] = -F,   W = I + sum_i lam_i Hess h_i,
 
 here with a general sparse LU (scipy SuperLU) on the full (n+m)x(n+m)
-matrix.  Start (u, lam) = (u_hat, 0); full steps; iterate until ||F||_inf stops
-shrinking (round-off floor) or falls below `atol`.  The result is the KKT
+matrix.  Start (u, lam) = (u_hat, 0).  Steps are damped by halving until the
+2-norm of F decreases (the textbook safeguard of Newton-Raphson for F = 0;
+near the solution the full step is always taken); iterate until ||F||_inf
+stops shrinking (round-off floor) or falls below `atol`.  The result is the KKT
 point; for linear h it is the affine projection
 u_hat - A^T (A A^T)^{-1} (A u_hat - b) (paper Table 1 row 'Au - b').
 
@@ -50,7 +52,7 @@ def kkt_residual(fam, u, uhat, lam):
     return u - uhat + J.T @ lam, fam.h(u)
 
 
-def project_sample(fam, uhat, max_iter=40, atol=0.0, return_info=False):
+def project_sample(fam, uhat, max_iter=100, atol=0.0, return_info=False):
     """Project one flattened sample onto {h = 0}.  Returns (u, lam[, info])."""
     uhat = np.asarray(uhat, dtype=np.float64).reshape(-1)
     n, m = fam.n, fam.m
@@ -67,18 +69,29 @@ def project_sample(fam, uhat, max_iter=40, atol=0.0, return_info=False):
         ru = u - uhat + J.T @ lam
         rh = fam.h(u)
         res = max(np.abs(ru).max(initial=0.0), np.abs(rh).max(initial=0.0))
+        res2 = np.sqrt(np.dot(ru, ru) + np.dot(rh, rh))
         history.append(res)
-        if best is None or res < best[0]:
-            best = (res, u.copy(), lam.copy(), it)
+        # progress is judged on the 2-norm, which the damped step decreases
+        if best is None or res2 < best[0]:
+            best = (res2, u.copy(), lam.copy(), it, res)
             stall = 0
         else:
             stall += 1
         if res <= atol or stall >= 2:
             break
         step = spla.spsolve(K, -np.concatenate([ru, rh]))
-        u = u + step[:n]
-        lam = lam + step[n:]
-    res, u, lam, it = best
+        # damped Newton-Raphson: halve the step until the 2-norm of the KKT
+        # residual F decreases (full steps near the solution)
+        f0 = np.sqrt(np.dot(ru, ru) + np.dot(rh, rh))
+        alpha = 1.0
+        for _ in range(40):
+            ut, lt = u + alpha * step[:n], lam + alpha * step[n:]
+            rut, rht = kkt_residual(fam, ut, uhat, lt)
+            if np.sqrt(np.dot(rut, rut) + np.dot(rht, rht)) <= (1.0 - 1e-4 * alpha) * f0 or f0 < 1e-12:
+                break
+            alpha *= 0.5
+        u, lam = ut, lt
+    _, u, lam, it, res = best
     info = dict(iters=it, res=res, history=history)
     return (u, lam, info) if return_info else (u, lam)
 
@@ -94,7 +107,7 @@ def adjoint_sample(fam, u, lam, grad_u):
     return sol[:n]
 
 
-def project_batch(batch, max_iter=40, indices=None):
+def project_batch(batch, max_iter=100, indices=None):
     """Project every sample of a synthgen Batch.  Returns packed (u, lam, iters)."""
     idx = range(len(batch)) if indices is None else indices
     u_out = np.array(batch.uhat, copy=True)
