@@ -123,19 +123,35 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true",
                     help="time the FP64 forward only (for profiler runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 512 MiB device-to-device 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "copies": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: every sample is independent and the library has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    import paper_2607_00095_amd as snap
-
     name = args.workload
     spec = dict(synthgen.CONFIGS[name]["kw"])
     batch = synthgen.make(name)
     B = len(batch)
+
+    # the CPU oracle runs first, in forked workers, before anything touches the GPU
+    cb = orc = None
+    if not args.no_cpu_baseline:
+        cb, orc = cpu_baseline(name, spec, batch)
+
+    import torch
+    import paper_2607_00095_amd as snap
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -231,8 +247,7 @@ def main():
                        "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name),
                        "kernel": KERNEL_NAMES[name], "algorithmic_bytes_per_launch": abytes}
 
-    if not args.no_cpu_baseline:
-        cb, orc = cpu_baseline(name, spec, batch)
+    if cb is not None:
         out["cpu_baseline"] = cb
         errs = []
         for i, uo in orc.items():

@@ -123,7 +123,7 @@ typedef struct snap_sample_stats {
 
 typedef struct snap_plan_s* snap_plan;
 
-/* Fill *opt with the defaults: tol_h 1e-10, tol_s 1e-10, max_newton 20,
+/* Fill *opt with the defaults: tol_h 1e-11, tol_s 1e-11, max_newton 20,
  * max_ls 30, FP64, no flags. */
 void snap_default_options(snap_options* opt);
 

@@ -86,8 +86,8 @@ def _check(rc: int, what: str):
 
 @dataclass
 class Options:
-    tol_h: float = 1e-10
-    tol_s: float = 1e-10
+    tol_h: float = 1e-11
+    tol_s: float = 1e-11
     max_newton: int = 20
     max_ls: int = 30
     precision: int = PREC_FP64

@@ -15,10 +15,10 @@
 #include "snap_device.hpp"
 
 namespace snap {
-int slab_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st);
-bool slab_supported(int nx, int nt);
-int band_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st);
-bool band_supported(int nx, int nt, bool mixed);
+int slab_class(int nx, int nt);
+int slab_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st);
+int band_class(int nx, int nt);
+int band_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st);
 size_t band_workspace_bytes(int nx, int nt, bool mixed);
 }  // namespace snap
 
@@ -26,11 +26,18 @@ using namespace snap;
 
 namespace {
 
+// Samples sharing one kernel instantiation (shapes may differ: every kernel
+// reads its sample's shape from the descriptor).  `kind` 0 = slab rows,
+// 1 = banded; `cls` = instantiation index; ids sorted by decreasing cost so
+// the longest samples start first.
 struct Group {
-  int family, nx, nt;
+  int kind, cls;
+  double cost = 0.0;
   std::vector<int32_t> ids;
   int32_t* d_ids = nullptr;
 };
+
+constexpr int kStreams = 4;   // groups are spread over this many internal streams
 
 }  // namespace
 
@@ -45,6 +52,8 @@ struct snap_plan_s {
   size_t ws_bytes = 0;
   int64_t total_vars = 0, total_rows = 0, total_aux = 0;
   int device = 0;
+  std::vector<hipStream_t> streams;     // fork/join of independent groups
+  std::vector<hipEvent_t> events;       // [0] fork, [1..] join per stream
 };
 
 namespace {
@@ -68,6 +77,8 @@ int64_t aux_of(const snap_sample_desc& d) {
 
 void free_plan(snap_plan p) {
   if (!p) return;
+  for (auto& e : p->events) (void)hipEventDestroy(e);
+  for (auto& s : p->streams) (void)hipStreamDestroy(s);
   for (auto& g : p->groups)
     if (g.d_ids) (void)hipFree(g.d_ids);
   if (p->d_descs) (void)hipFree(p->d_descs);
@@ -86,8 +97,8 @@ extern "C" {
 
 void snap_default_options(snap_options* opt) {
   if (!opt) return;
-  opt->tol_h = 1e-10;
-  opt->tol_s = 1e-10;
+  opt->tol_h = 1e-11;
+  opt->tol_s = 1e-11;
   opt->max_newton = 20;
   opt->max_ls = 30;
   opt->precision = SNAP_PREC_FP64;
@@ -110,7 +121,8 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
   p->descs.assign(descs_host, descs_host + batch);
   if (hipGetDevice(&p->device) != hipSuccess) { free_plan(p); return SNAP_EHIP; }
 
-  std::map<std::tuple<int, int, int>, size_t> gidx;
+  std::map<std::pair<int, int>, size_t> gidx;
+  std::vector<double> cost(batch, 0.0);
   p->ws_off.assign(batch, 0);
   size_t ws = 0;
   for (int32_t s = 0; s < batch; ++s) {
@@ -120,33 +132,59 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
     }
     const int64_t m = rows_of(d);
     if (m < 0) { free_plan(p); return SNAP_EUNSUPPORTED; }
-    bool ok = false;
+    int kind = -1, cls = -1;
     size_t need = 0;
     if (d.family == SNAP_MASS_IC || d.family == SNAP_FISHER_KPP) {
-      ok = slab_supported(d.nx, d.nt);
-      if (d.family == SNAP_FISHER_KPP && !(d.dt > 0.0)) ok = false;
+      kind = 0;
+      cls = slab_class(d.nx, d.nt);
+      if (d.family == SNAP_FISHER_KPP && !(d.dt > 0.0)) cls = -1;
+      cost[s] = (double)d.nx * d.nt;
     } else if (d.family == SNAP_BURGERS_LF) {
-      ok = band_supported(d.nx, d.nt, mixed) && d.dt > 0.0 && d.dx > 0.0;
-      need = band_workspace_bytes(d.nx, d.nt, mixed);
+      kind = 1;
+      cls = (d.dt > 0.0 && d.dx > 0.0) ? band_class(d.nx, d.nt) : -1;
+      if (cls > 0) need = band_workspace_bytes(d.nx, d.nt, mixed);
+      // factorization work ~ rows x (block bandwidth)^2
+      cost[s] = (double)d.nx * (d.nt - 1) * (double)(cls + 1) * (cls + 1) * 256.0;
     }
-    if (!ok) { free_plan(p); return SNAP_EUNSUPPORTED; }
+    if (cls < 0) { free_plan(p); return SNAP_EUNSUPPORTED; }
     p->ws_off[s] = (int64_t)ws;
     ws += (need + 255) & ~(size_t)255;
     const int64_t nvar = (int64_t)d.nx * d.ny * d.nt;
     p->total_vars = std::max(p->total_vars, d.var_off + nvar);
     p->total_rows = std::max(p->total_rows, d.row_off + m);
     p->total_aux = std::max(p->total_aux, d.aux_off + aux_of(d));
-    auto key = std::make_tuple(d.family, d.nx, d.nt);
+    auto key = std::make_pair(kind, cls);
     auto it = gidx.find(key);
+    size_t gi;
     if (it == gidx.end()) {
-      gidx[key] = p->groups.size();
-      p->groups.push_back(Group{d.family, d.nx, d.nt, {}, nullptr});
-      p->groups.back().ids.push_back(s);
+      gi = p->groups.size();
+      gidx[key] = gi;
+      Group g;
+      g.kind = kind;
+      g.cls = cls;
+      p->groups.push_back(g);
     } else {
-      p->groups[it->second].ids.push_back(s);
+      gi = it->second;
     }
+    p->groups[gi].ids.push_back(s);
+    p->groups[gi].cost += cost[s];
   }
   p->ws_bytes = std::max<size_t>(ws, 256);
+  // longest samples first inside a group; most expensive groups first
+  for (auto& g : p->groups)
+    std::stable_sort(g.ids.begin(), g.ids.end(),
+                     [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+  std::stable_sort(p->groups.begin(), p->groups.end(),
+                   [](const Group& x, const Group& y) { return x.cost > y.cost; });
+  if (p->groups.size() > 1) {
+    const int ns = std::min<int>(kStreams, (int)p->groups.size());
+    p->events.resize(ns + 1, nullptr);
+    for (auto& e : p->events)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { free_plan(p); return SNAP_EHIP; }
+    p->streams.resize(ns, nullptr);
+    for (auto& st : p->streams)
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) { free_plan(p); return SNAP_EHIP; }
+  }
 
   if (batch > 0) {
     if (hipMalloc(&p->d_descs, sizeof(snap_sample_desc) * batch) != hipSuccess ||
@@ -183,17 +221,29 @@ int snap_plan_sizes(snap_plan plan, int64_t* total_vars, int64_t* total_rows, in
   return SNAP_SUCCESS;
 }
 
-static int run(snap_plan plan, KernelArgs a, hipStream_t st) {
+static int launch_group(const snap_plan plan, KernelArgs a, const Group& g, hipStream_t st) {
   const bool mixed = plan->opt.precision == SNAP_PREC_MIXED;
-  for (auto& g : plan->groups) {
-    a.order = g.d_ids;
-    a.count = (int32_t)g.ids.size();
-    int rc = SNAP_EUNSUPPORTED;
-    if (g.family == SNAP_MASS_IC || g.family == SNAP_FISHER_KPP)
-      rc = slab_launch(a, g.nx, g.nt, mixed, st);
-    else if (g.family == SNAP_BURGERS_LF)
-      rc = band_launch(a, g.nx, g.nt, mixed, st);
+  a.order = g.d_ids;
+  a.count = (int32_t)g.ids.size();
+  return g.kind == 0 ? slab_launch(a, g.cls, mixed, st) : band_launch(a, g.cls, mixed, st);
+}
+
+// One group: launch on the caller's stream.  Several: fork onto the plan's
+// streams (groups are independent), largest groups first, round robin, and
+// join back so the caller's stream orders everything after the call.
+static int run(snap_plan plan, KernelArgs a, hipStream_t st) {
+  if (plan->groups.size() == 1) return launch_group(plan, a, plan->groups[0], st);
+  const int ns = (int)plan->streams.size();
+  if (hipEventRecord(plan->events[0], st) != hipSuccess) return SNAP_EHIP;
+  for (int i = 0; i < ns; ++i)
+    if (hipStreamWaitEvent(plan->streams[i], plan->events[0], 0) != hipSuccess) return SNAP_EHIP;
+  for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
+    const int rc = launch_group(plan, a, plan->groups[gi], plan->streams[gi % ns]);
     if (rc != 0) return rc;
+  }
+  for (int i = 0; i < ns; ++i) {
+    if (hipEventRecord(plan->events[1 + i], plan->streams[i]) != hipSuccess) return SNAP_EHIP;
+    if (hipStreamWaitEvent(st, plan->events[1 + i], 0) != hipSuccess) return SNAP_EHIP;
   }
   return SNAP_SUCCESS;
 }

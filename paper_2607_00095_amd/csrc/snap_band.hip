@@ -95,8 +95,10 @@ struct Ctx {
 
 // workspace layout of one sample (byte offsets, 256-aligned)
 struct WsLayout {
-  size_t hdr, L, Dg, Y, rin, rvec, lamp, p, t, res, total;
+  size_t hdr, L, Dg, Y, rin, rvec, lamp, p, t, res, acol, aval, total;
 };
+
+constexpr int kContrib = 16;   // stencil contributions to one row of S (4 variables x 4 rows)
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -121,6 +123,8 @@ __host__ __device__ inline WsLayout ws_layout(int nx, int nt, int BB, size_t rsi
   w.p = o; o += align256(n * 8);
   w.t = o; o += align256(n * 8);
   w.res = o; o += align256(m * 8);
+  w.acol = o; o += align256(M * kContrib * 4);
+  w.aval = o; o += align256(M * kContrib * 8);
   w.total = o;
   return w;
 }
@@ -213,51 +217,70 @@ __device__ __forceinline__ double block_max(double v, double (*red)[4], int slot
 // Row r (internal order) of S and of the right-hand side h - J W^{-1} d,
 // scattered into the staging tile row `a` for columns [lo, hi) (block-aligned):
 // S[r, r'] = sum over variables v of row r of J(r,v) J(r',v) / W(v).
-template <int BB, typename R>
-__device__ __forceinline__ void scatter_s(const Ctx& C, int I, int a, int lo, int hi, R (*NR)[kTL],
-                                          int rk, int rx, double val) {
-  const int col = rk * C.nx + pos_of(rx, C.nx);
-  if (col >= lo && col < hi) {
-    const int cb = col / kT, cc = col - cb * kT;
-    NR[I - cb][a * kLd + cc] += (R)val;
+// Contributions of row r (internal order) of S = J W^{-1} J^T and of the
+// right-hand side h - J W^{-1} g: for each of the four variables v of row
+// (k, x) and each row r' touching v, the value J(r,v) J(r',v) / W(v) with the
+// column of r' (a column may appear more than once when Nx is tiny; the
+// scatter adds them).  Computed for all rows in one parallel pass before the
+// factorization, so the factorization only scatters prefetched pairs.
+template <int NW>
+__device__ void assemble_all(const Ctx& C, const WsLayout& WL) {
+  int* acol = (int*)(C.ws + WL.acol);
+  double* aval = (double*)(C.ws + WL.aval);
+  double* rvec = (double*)(C.ws + WL.rvec);
+  double* rin = (double*)(C.ws + WL.rin);
+  const int nx = C.nx;
+  for (int r = threadIdx.x; r < C.M; r += NW * kWave) {
+    int* col = acol + (size_t)r * kContrib;
+    double* val = aval + (size_t)r * kContrib;
+    if (r >= C.m) {                    // padding row: identity
+#pragma unroll
+      for (int t = 0; t < kContrib; ++t) { col[t] = r; val[t] = t == 0 ? 1.0 : 0.0; }
+      rin[r] = 0.0;
+      continue;
+    }
+    const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
+    double rhs = C.bwd ? 0.0 : h_row(C, k, x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      // the four variables of row (k, x): (k+1, x), (k, x), (k, x+1), (k, x-1)
+      const int kk = (e == 0) ? k + 1 : k;
+      const int y = (e <= 1) ? x : (e == 2 ? wrap(x + 1, nx) : wrap(x - 1, nx));
+      const size_t v = (size_t)kk * nx + y;
+      const double uy = C.u[v];
+      const double al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
+      const double sv = al / w_at(C, kk, y);
+      rhs -= sv * gres(C, kk, y);
+      // rows touching variable (kk, y): (kk-1, y) with 1; (kk, y-1), (kk, y), (kk, y+1)
+      const bool up = kk >= 1, own = kk <= C.nt - 2;
+      col[4 * e + 0] = up ? (kk - 1) * nx + pos_of(y, nx) : r;
+      val[4 * e + 0] = up ? sv : 0.0;
+      col[4 * e + 1] = own ? kk * nx + pos_of(wrap(y - 1, nx), nx) : r;
+      val[4 * e + 1] = own ? sv * (C.q * uy - C.c) : 0.0;
+      col[4 * e + 2] = own ? kk * nx + pos_of(y, nx) : r;
+      val[4 * e + 2] = own ? sv * C.cd : 0.0;
+      col[4 * e + 3] = own ? kk * nx + pos_of(wrap(y + 1, nx), nx) : r;
+      val[4 * e + 3] = own ? sv * (-C.q * uy - C.c) : 0.0;
+    }
+    rvec[(size_t)k * nx + x] = rhs;
+    rin[r] = rhs;
   }
+  __syncthreads();
 }
 
+// scatter the prefetched contributions of row a of block row I into the staging tile
 template <int BB, typename R>
-__device__ void assemble_row(const Ctx& C, int r, int a, int I, R (*NR)[kTL], double* rhs_out,
-                             double* rvec, double* rin) {
-  const int nx = C.nx;
-  if (r >= C.M) { *rhs_out = 0.0; return; }
-  if (r >= C.m) {            // padding row: identity
-    NR[0][a * kLd + a] = (R)1.0;
-    *rhs_out = 0.0;
-    rin[r] = 0.0;
-    return;
-  }
-  const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
+__device__ __forceinline__ void scatter_row(int I, int a, const int* col, const double* val,
+                                            R (*NR)[kTL]) {
   const int lo = (I - BB) * kT, hi = (I + 1) * kT;
-  double rhs = C.bwd ? 0.0 : h_row(C, k, x);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    // the four variables of row (k, x): (k+1, x), (k, x), (k, x+1), (k, x-1)
-    const int kk = (e == 0) ? k + 1 : k;
-    const int y = (e <= 1) ? x : (e == 2 ? wrap(x + 1, nx) : wrap(x - 1, nx));
-    const size_t v = (size_t)kk * nx + y;
-    const double uy = C.u[v];
-    const double al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
-    const double s = al / w_at(C, kk, y);
-    rhs -= s * gres(C, kk, y);
-    // rows touching variable (kk, y): (kk-1, y) with 1; (kk, y-1), (kk, y), (kk, y+1)
-    if (kk >= 1) scatter_s<BB, R>(C, I, a, lo, hi, NR, kk - 1, y, s);
-    if (kk <= C.nt - 2) {
-      scatter_s<BB, R>(C, I, a, lo, hi, NR, kk, wrap(y - 1, nx), s * (C.q * uy - C.c));
-      scatter_s<BB, R>(C, I, a, lo, hi, NR, kk, y, s * C.cd);
-      scatter_s<BB, R>(C, I, a, lo, hi, NR, kk, wrap(y + 1, nx), s * (-C.q * uy - C.c));
+  for (int t = 0; t < kContrib; ++t) {
+    const int cc = col[t];
+    if (cc >= lo && cc < hi) {
+      const int cb = cc / kT;
+      NR[I - cb][a * kLd + (cc - cb * kT)] += (R)val[t];
     }
   }
-  *rhs_out = rhs;
-  rvec[(size_t)k * nx + x] = rhs;
-  rin[r] = rhs;
 }
 
 // ------------------------------------------------------------------ factor
@@ -316,22 +339,54 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     acc[s] = v;
   };
 
+  assemble_all<NW>(C, WL);
+  const int* acol = (const int*)(C.ws + WL.acol);
+  const double* aval = (const double*)(C.ws + WL.aval);
+  // prefetch registers of wavefront 1, lanes 0..15 (row `lane` of the next entering block row)
+  int pcol[kContrib];
+  double pval[kContrib];
+  double prhs = 0.0;
+  auto prefetch_row = [&](int I) {
+    const int r = I * kT + lane;
+    if (I < C.NB) {
+#pragma unroll
+      for (int t = 0; t < kContrib; ++t) {
+        pcol[t] = acol[(size_t)r * kContrib + t];
+        pval[t] = aval[(size_t)r * kContrib + t];
+      }
+      prhs = rin[r];
+    } else {
+#pragma unroll
+      for (int t = 0; t < kContrib; ++t) { pcol[t] = -1; pval[t] = 0.0; }
+      prhs = 0.0;
+    }
+  };
+  (void)rvec;
+
   // ---- initial window: block rows 0..BB
   for (int I = 0; I <= BB; ++I) {
     zero_nr();
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x < kT) {
-      double rr;
-      assemble_row<BB, R>(C, I * kT + threadIdx.x, threadIdx.x, I, sh.NR, &rr, rvec, rin);
-      sh.ring[(I % (BB + 1)) * kT + threadIdx.x] = (I < C.NB) ? rr : 0.0;
+      const int r = I * kT + threadIdx.x;
+      int cl[kContrib];
+      double vl[kContrib];
+#pragma unroll
+      for (int t = 0; t < kContrib; ++t) {
+        cl[t] = (I < C.NB) ? acol[(size_t)r * kContrib + t] : -1;
+        vl[t] = (I < C.NB) ? aval[(size_t)r * kContrib + t] : 0.0;
+      }
+      scatter_row<BB, R>(I, threadIdx.x, cl, vl, sh.NR);
+      sh.ring[(I % (BB + 1)) * kT + threadIdx.x] = (I < C.NB) ? rin[r] : 0.0;
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int s = 0; s < SPW; ++s)
       if (sd[s] >= 0 && sd[s] <= I && slot_row(s, 0) == I) load_nr(s, sd[s]);
-    __syncthreads();
+    lds_barrier();
   }
 
+  if (w == 1 && lane < kT) prefetch_row(BB + 1);
   int bad = 0;
   for (int J = 0; J < C.NB; ++J) {
     // (a) gather the panel column J into LDS; clear the staging area
@@ -344,7 +399,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       }
     }
     zero_nr();
-    __syncthreads();
+    lds_barrier();
 
     // (b) wavefront 0: LDL^T of the diagonal block; wavefront 1: next block row
     if (w == 0) {
@@ -408,12 +463,13 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       nonpos = __any(nonpos);
       if (lane == 0 && nonpos) sh.flag[0] = 1;
     } else if (w == 1 && lane < kT) {
-      const int I = J + BB + 1;
-      double rr = 0.0;
-      if (I < C.NB) assemble_row<BB, R>(C, I * kT + lane, lane, I, sh.NR, &rr, rvec, rin);
-      sh.newr[lane] = rr;
+      // entering block row J+BB+1 from the prefetched contributions; then
+      // prefetch the one after it
+      scatter_row<BB, R>(J + BB + 1, lane, pcol, pval, sh.NR);
+      sh.newr[lane] = prhs;
+      prefetch_row(J + BB + 2);
     }
-    __syncthreads();
+    lds_barrier();
 
     // (c) panel solve L(J+d, J) = S(J+d, J) T for d >= 1
 #pragma unroll
@@ -435,7 +491,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
         Lgd[Mfma<R>::row(lk, e) * kT + li] = res[e];
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // (d) forward-substitution update, trailing update, entering row
     for (int t = threadIdx.x; t < kT * BB; t += NW * kWave) {
@@ -470,90 +526,124 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       __builtin_amdgcn_sched_barrier(0);
     }
     if (threadIdx.x < kT) sh.ring[(J % (BB + 1)) * kT + threadIdx.x] = sh.newr[threadIdx.x];
-    __syncthreads();
+    lds_barrier();
   }
   bad = sh.flag[0];
-  __syncthreads();
+  __syncthreads();            // factor (global) visible to the sweeps
   if (threadIdx.x == 0) sh.flag[0] = 0;
-  __syncthreads();
+  lds_barrier();
   return bad;
 }
 
 // ------------------------------------------------------------------ solves
-// forward substitution y = L^{-1} rin with the stored factor
+// forward substitution y = L^{-1} rin with the stored factor.  Threads
+// t < 16*BB own row (t % 16) of block L(J+1+t/16, J); threads 16*BB..16*BB+15
+// own a row of L_JJ^{-1}; each keeps its 16 values of the next panel in flight.
 template <int BB, int NW, typename R>
-__device__ __attribute__((always_inline)) void forward_sweep(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh,
-                              const double* rin, double* Y) {
+__device__ __attribute__((always_inline)) void forward_sweep(
+    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* rin, double* Y) {
+  static_assert(NW * kWave >= kT * (BB + 1), "forward sweep needs 16*(BB+1) threads");
   const R* Lg = (const R*)(C.ws + WL.L);
-  for (int t = threadIdx.x; t < (BB + 1) * kT; t += NW * kWave) {
-    const int I = t / kT, a = t - I * kT;
-    sh.ring[t] = (I < C.NB) ? rin[(size_t)I * kT + a] : 0.0;
+  const int t = threadIdx.x;
+  const bool offd = t < kT * BB, diag = t >= kT * BB && t < kT * (BB + 1);
+  const int d = offd ? 1 + t / kT : 0, a = offd ? t % kT : t - kT * BB;
+  for (int i = t; i < (BB + 1) * kT; i += NW * kWave) {
+    const int I = i / kT, aa = i - I * kT;
+    sh.ring[i] = (I < C.NB) ? rin[(size_t)I * kT + aa] : 0.0;
   }
-  __syncthreads();
+  R cur[kT], nxt[kT];
+  auto load = [&](int J, R* dst) {
+    if ((offd || diag) && J < C.NB) {
+      const R* src = Lg + ((size_t)J * (BB + 1) + d) * 256 + a * kT;
+#pragma unroll
+      for (int c = 0; c < kT; ++c) dst[c] = src[c];
+    }
+  };
+  load(0, cur);
+  lds_barrier();
   for (int J = 0; J < C.NB; ++J) {
-    const R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
-    if (threadIdx.x < kT) {
+    load(J + 1, nxt);
+    if (diag) {
       const double* rJ = &sh.ring[(J % (BB + 1)) * kT];
-      const int i = threadIdx.x;
       double y = 0.0;
 #pragma unroll
-      for (int cc = 0; cc < kT; ++cc) y += (double)Lgd[i * kT + cc] * rJ[cc];
-      sh.yJ[i] = y;
-      Y[(size_t)J * kT + i] = y;
+      for (int c = 0; c < kT; ++c) y += (double)cur[c] * rJ[c];
+      sh.yJ[a] = y;
+      Y[(size_t)J * kT + a] = y;
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kT * BB; t += NW * kWave) {
-      const int d = 1 + t / kT, a = t - (d - 1) * kT;
-      const int I = J + d;
-      if (I < C.NB) {
-        const R* Lb = Lgd + (size_t)d * 256 + a * kT;
-        double s = 0.0;
+    lds_barrier();
+    if (offd && J + d < C.NB) {
+      double s = 0.0;
 #pragma unroll
-        for (int cc = 0; cc < kT; ++cc) s += (double)Lb[cc] * sh.yJ[cc];
-        sh.ring[(I % (BB + 1)) * kT + a] -= s;
-      }
+      for (int c = 0; c < kT; ++c) s += (double)cur[c] * sh.yJ[c];
+      sh.ring[((J + d) % (BB + 1)) * kT + a] -= s;
     }
-    __syncthreads();
-    if (threadIdx.x < kT) {
+    lds_barrier();
+    if (t < kT) {
       const int I = J + BB + 1;
-      sh.ring[(J % (BB + 1)) * kT + threadIdx.x] = (I < C.NB) ? rin[(size_t)I * kT + threadIdx.x] : 0.0;
+      sh.ring[(J % (BB + 1)) * kT + t] = (I < C.NB) ? rin[(size_t)I * kT + t] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kT; ++c) cur[c] = nxt[c];
+    lds_barrier();
   }
+  __syncthreads();            // Y visible to every wavefront
 }
 
-// backward substitution x = L^{-T} D^{-1} Y; x is written in canonical row order
+// backward substitution x = L^{-T} D^{-1} Y; x is written in canonical row
+// order.  Thread (c = t % 16, g = t / 16) accumulates the (d, a) pairs
+// pq = g, g + NG, ... of sum_{d,a} L(J+d,J)[a][c] x_{J+d}[a] and holds one
+// element of L_JJ^{-1}; the next panel's values are loaded one step ahead.
 template <int BB, int NW, typename R>
-__device__ __attribute__((always_inline)) void backward_sweep(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh,
-                               const double* Y, double* xout) {
+__device__ __attribute__((always_inline)) void backward_sweep(
+    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* Y, double* xout) {
+  constexpr int NT = NW * kWave;
+  constexpr int NG = NT / kT;                       // 16-thread groups
+  constexpr int NPQ = (BB * kT + NG - 1) / NG;      // (d, a) pairs per thread
   const R* Lg = (const R*)(C.ws + WL.L);
   const double* Dg = (const double*)(C.ws + WL.Dg);
   const int t = threadIdx.x;
-  const int cc = t & 15, grp = t >> 4;        // column of the block, partial-sum group
-  constexpr int NG = NW * kWave / kT;          // groups of 16 threads
-  for (int i = t; i < (BB + 1) * kT; i += NW * kWave) sh.ring[i] = 0.0;
-  __syncthreads();
-  for (int J = C.NB - 1; J >= 0; --J) {
-    const R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
-    // partial sums of sum_{d,a} L(J+d,J)[a][c] x_{J+d}[a] over (d, a) pairs
-    double s = 0.0;
-    for (int pq = grp; pq < BB * kT; pq += NG) {
+  const int cc = t & 15, grp = t >> 4;
+  for (int i = t; i < (BB + 1) * kT; i += NT) sh.ring[i] = 0.0;
+  R cur[NPQ], nxt[NPQ];
+  R dcur = 0, dnxt = 0;       // element (t / 16, t % 16) of L_JJ^{-1} (t < 256)
+  double ycur = 0.0, ynxt = 0.0;
+  auto load = [&](int J, R* dst, R& dg, double& yv) {
+    if (J < 0) return;
+    const R* base = Lg + (size_t)J * (BB + 1) * 256;
+#pragma unroll
+    for (int i = 0; i < NPQ; ++i) {
+      const int pq = grp + NG * i;
       const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
-      if (J + d < C.NB)
-        s += (double)Lgd[(size_t)d * 256 + a * kT + cc] * sh.ring[((J + d) % (BB + 1)) * kT + a];
+      dst[i] = (pq < BB * kT && J + d < C.NB) ? base[(size_t)d * 256 + a * kT + cc] : (R)0;
+    }
+    if (t < 256) dg = base[t];
+    if (t < kT) yv = Y[(size_t)J * kT + t] / Dg[(size_t)J * kT + t];
+  };
+  load(C.NB - 1, cur, dcur, ycur);
+  lds_barrier();
+  for (int J = C.NB - 1; J >= 0; --J) {
+    load(J - 1, nxt, dnxt, ynxt);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPQ; ++i) {
+      const int pq = grp + NG * i;
+      const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
+      if (pq < BB * kT) s += (double)cur[i] * sh.ring[((J + d) % (BB + 1)) * kT + a];
     }
     sh.part[t] = s;
-    __syncthreads();
+    if (t < 256) sh.Xw[(t >> 4) * kLd + (t & 15)] = (double)dcur;
+    lds_barrier();
     if (t < kT) {
       double acc = 0.0;
       for (int q = 0; q < NG; ++q) acc += sh.part[q * kT + t];
-      sh.yJ[t] = Y[(size_t)J * kT + t] / Dg[(size_t)J * kT + t] - acc;
+      sh.yJ[t] = ycur - acc;
     }
-    __syncthreads();
+    lds_barrier();
     if (t < kT) {
       double x = 0.0;
 #pragma unroll
-      for (int c2 = 0; c2 < kT; ++c2) x += (double)Lgd[c2 * kT + t] * sh.yJ[c2];   // L^{-T}
+      for (int c2 = 0; c2 < kT; ++c2) x += sh.Xw[c2 * kLd + t] * sh.yJ[c2];   // L_JJ^{-T}
       sh.ring[(J % (BB + 1)) * kT + t] = x;
       const int r = J * kT + t;
       if (r < C.m) {
@@ -561,8 +651,13 @@ __device__ __attribute__((always_inline)) void backward_sweep(const Ctx& C, cons
         xout[(size_t)k * C.nx + fold_x(px, C.nx)] = x;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPQ; ++i) cur[i] = nxt[i];
+    dcur = dnxt;
+    ycur = ynxt;
+    lds_barrier();
   }
+  __syncthreads();            // x visible to every wavefront
 }
 
 // res = rvec - S x (float64, matrix free), x canonical; returns max |res|
@@ -873,16 +968,17 @@ bool band_supported(int nx, int nt, bool mixed) {
   return nx >= 3 && nt >= 2 && pick_bb(band_bb(nx, nt)) > 0 && (int64_t)nx * nt < (1 << 30);
 }
 
+// Kernel class of a shape: the instantiated block half-bandwidth.
+int band_class(int nx, int nt) { return band_supported(nx, nt, false) ? pick_bb(band_bb(nx, nt)) : -1; }
+
 size_t band_workspace_bytes(int nx, int nt, bool mixed) {
   const int bb = pick_bb(band_bb(nx, nt));
   return ws_layout(nx, nt, bb, mixed ? sizeof(float) : sizeof(double)).total;
 }
 
-int band_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st) {
+int band_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st) {
   if (a.count == 0) return 0;
-  if (!band_supported(nx, nt, mixed)) return SNAP_EUNSUPPORTED;
-  const int bb = pick_bb(band_bb(nx, nt));
-  return mixed ? launch_bb<float>(bb, a, st) : launch_bb<double>(bb, a, st);
+  return mixed ? launch_bb<float>(cls, a, st) : launch_bb<double>(cls, a, st);
 }
 
 }  // namespace snap

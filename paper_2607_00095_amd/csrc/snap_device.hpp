@@ -34,33 +34,62 @@ __device__ __forceinline__ double bcast_first(double v) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ float bcast_first(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+// Wavefront reductions with DPP (VALU only, no LDS round trips): an
+// inclusive prefix within each row of 16 lanes (row_shr 1, 2, 4, 8), then
+// row_bcast:15 / row_bcast:31 fold rows together, so lane 63 holds the
+// result; it is broadcast so every lane holds bit-identical values.
+// Out-of-row sources read 0 (bound_ctrl): valid for sums and for maxima of
+// non-negative values, which is how these are used.
+template <int CTRL, int ROWMASK, bool BC>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWMASK, 0xf, BC);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWMASK, 0xf, BC);
+  return __hiloint2double(hi, lo);
 }
 
-// Butterfly sum over the 64 lanes; the result of lane 0 is broadcast so every
-// lane holds bit-identical values.
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return bcast_first(v);
+__device__ __forceinline__ double lane63(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return bcast_first(v);
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0x111, 0xf, true>(v);    // row_shr:1
+  v += dpp_d<0x112, 0xf, true>(v);    // row_shr:2
+  v += dpp_d<0x114, 0xf, true>(v);    // row_shr:4
+  v += dpp_d<0x118, 0xf, true>(v);    // row_shr:8
+  v += dpp_d<0x142, 0xa, false>(v);   // row_bcast:15 into rows 1, 3
+  v += dpp_d<0x143, 0xc, false>(v);   // row_bcast:31 into rows 2, 3
+  return lane63(v);
+}
+
+// maximum of non-negative values
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_d<0x111, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x112, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x114, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x118, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x142, 0xa, false>(v));
+  v = fmax(v, dpp_d<0x143, 0xc, false>(v));
+  return lane63(v);
+}
+
+// Barriers that order LDS only: they do not wait for outstanding global
+// loads or stores, so prefetches and factor write-back stay in flight.
+// Global data exchanged between wavefronts still needs __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // Order LDS accesses of one wavefront (no cross-wave synchronization).
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
 }  // namespace snap

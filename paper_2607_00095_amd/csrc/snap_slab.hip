@@ -19,14 +19,14 @@
 // leaving a symmetric tridiagonal system in time, solved by parallel cyclic
 // reduction inside one wavefront.
 //
-// One workgroup (8 wavefronts) owns one sample for the whole Newton loop.
-// Wavefront w owns time slabs w, w+8, ...; lane l owns x = l, l+64, ...; the
+// One workgroup (16 wavefronts) owns one sample for the whole Newton loop.
+// Wavefront w owns time slabs w, w+16, ...; lane l owns x = l, l+64, ...; the
 // field stays in registers and every slab sum is a wavefront reduction.
 #include "snap_device.hpp"
 
 namespace snap {
 
-constexpr int kSlabWaves = 8;
+constexpr int kSlabWaves = 16;
 constexpr int kSlabThreads = kSlabWaves * kWave;
 constexpr int kMaxNt = 128;
 
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
   const double c = f2 ? D.dt * D.p0 : 0.0;
   const double wfloor = 0.1;
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
   const bool bwd = A.backward != 0;
 
   __shared__ SlabShared sh;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
   if (bwd) {
     // W is taken at lam*; the adjoint right-hand side uses J W^{-1} grad_u only,
     // so the multipliers entering the stationarity residual are zero
-    __syncthreads();
+    lds_barrier();
     for (int k = threadIdx.x; k < kMaxNt; k += kSlabThreads) sh.lam[k] = 0.0;
 #pragma unroll
     for (int j = 0; j < XPL; ++j) lamic[j] = 0.0;
@@ -204,11 +204,11 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
     int nf = __any(nonfinite) ? 1 : 0;
     if (lane == 0) { sh.red[w][0] = mx; sh.red[w][1] = (double)nf; }
   }
-  __syncthreads();
+  lds_barrier();
   double uscale = 0.0, nfin = 0.0;
   for (int q = 0; q < kSlabWaves; ++q) { uscale = fmax(uscale, sh.red[q][0]); nfin += sh.red[q][1]; }
   uscale += 1.0;
-  __syncthreads();
+  lds_barrier();
 
   double mu = 0.0;
   int iters = 0, backtracks = 0, refines = 0, status = SNAP_ST_MAX_ITER;
@@ -248,6 +248,8 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
         sh.S1[k] = S1; sh.S2[k] = S2; sh.Sd[k] = Sd;
         sh.Sa2[k] = Sa2; sh.Sa[k] = Sa; sh.Sad[k] = Sad;
       }
+      // one slab's reductions at a time (bounds register pressure)
+      __builtin_amdgcn_sched_barrier(0);
     }
     // IC rows live on slab 0, owned by wavefront 0 (s = 0)
     double ric[XPL];
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
     }
     st_w = wave_max(st_w);
     if (lane == 0) sh.red[w][0] = st_w;
-    __syncthreads();
+    lds_barrier();
 
     // ------------------------------------------------ wavefront 0: rows, test, solve
     if (w == 0) {
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
         for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.lam[k];
       }
     }
-    __syncthreads();
+    lds_barrier();
     const int done = sh.flag[0];
     if (done) {
       status = done == 1 ? SNAP_ST_CONVERGED : (done == 2 ? SNAP_ST_NONFINITE : SNAP_ST_MAX_ITER);
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
       pp = wave_sum(pp); dd = wave_sum(dd);
       if (lane == 0) { sh.red[w][1] = pp; sh.red[w][2] = dd; }
     }
-    __syncthreads();
+    lds_barrier();
     lmax = fmax(lmax, sh.scal[4]);
     mu = fmax(mu, 1.1 * lmax + 1e-8);
     // the merit change along p is formed from differences (alpha d.p +
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
     for (int q = 0; q < kSlabWaves; ++q) { pp += sh.red[q][1]; dd += sh.red[q][2]; }
     const double h1_0 = sh.scal[3];
     const double dphi = dd - mu * h1_0;
-    __syncthreads();
+    lds_barrier();
 
     // ------------------------------------------------ backtracking line search
     double alpha = 1.0;
@@ -435,6 +437,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
         }
         S1 = wave_sum(S1); S2 = wave_sum(S2);
         if (lane == 0) { sh.S1[k] = S1; sh.S2[k] = S2; }
+        __builtin_amdgcn_sched_barrier(0);
       }
       if (w == 0) {
         double hic1 = 0.0;
@@ -448,7 +451,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
         hic1 = wave_sum(hic1);
         if (lane == 0) sh.scal[5] = hic1;
       }
-      __syncthreads();
+      lds_barrier();
       if (w == 0) {
         double h1 = sh.scal[5];
         for (int k = lane; k < nr; k += kWave) {
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
         int ok = (dphi_t <= 1e-4 * alpha * dphi) || !(dphi < 0.0) || hinf <= 1e-6 ? 1 : 0;
         if (lane == 0) sh.flag[1] = ok;
       }
-      __syncthreads();
+      lds_barrier();
       if (sh.flag[1]) { accepted = 1; break; }
       alpha *= 0.5;
       ++backtracks;
@@ -481,7 +484,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
         if (xof(j) < nx) u[s][j] += alpha * step_at(s, j, k, u[s][j]);
     }
     // every thread computed its step with the old u above; now update lam, W
-    __syncthreads();
+    lds_barrier();
     if (w == 0) {
 #pragma unroll
       for (int j = 0; j < XPL; ++j) lamic[j] += alpha * (lampic[j] - lamic[j]);
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
       sh.W[k] = fmax(1.0 + 2.0 * c * l, wfloor);
     }
     ++iters;
-    __syncthreads();
+    lds_barrier();
   }
 
   // ---------------------------------------------------------------- outputs
@@ -531,36 +534,43 @@ using SlabLaunch = void (*)(const KernelArgs&, hipStream_t);
 
 template <int SPW, int XPL, typename TS>
 static void launch_slab(const KernelArgs& a, hipStream_t st) {
-  constexpr bool ureg = SPW * XPL <= 32;
+  constexpr bool ureg = SPW * XPL <= 16;
   hipLaunchKernelGGL((slab_kernel<SPW, XPL, ureg, TS>), dim3(a.count), dim3(kSlabThreads), 0, st, a);
 }
 
 template <typename TS>
 static SlabLaunch pick_slab(int spw, int xpl) {
 #define SNAP_SLAB_CASE(S, X) if (spw <= S && xpl == X) return &launch_slab<S, X, TS>;
-#define SNAP_SLAB_ROW(X) SNAP_SLAB_CASE(2, X) SNAP_SLAB_CASE(4, X) SNAP_SLAB_CASE(8, X) \
-                         SNAP_SLAB_CASE(13, X) SNAP_SLAB_CASE(16, X)
+#define SNAP_SLAB_ROW(X) SNAP_SLAB_CASE(1, X) SNAP_SLAB_CASE(2, X) SNAP_SLAB_CASE(4, X) \
+                         SNAP_SLAB_CASE(7, X) SNAP_SLAB_CASE(8, X)
   SNAP_SLAB_ROW(1) SNAP_SLAB_ROW(2) SNAP_SLAB_ROW(3) SNAP_SLAB_ROW(4)
 #undef SNAP_SLAB_ROW
 #undef SNAP_SLAB_CASE
   return nullptr;
 }
 
-// Host entry used by the plan: launch one workgroup per listed sample, all of
-// which share (nx, nt) class (spw, xpl).
-int slab_launch(const KernelArgs& a, int nx, int nt, bool mixed, hipStream_t st) {
-  if (a.count == 0) return 0;
-  if (nt < 1 || nt > kMaxNt || nx < 1 || nx > 4 * kWave) return SNAP_EUNSUPPORTED;
+// Kernel class of a (nx, nt) shape: index of the (SPW, XPL) instantiation, or -1.
+int slab_class(int nx, int nt) {
+  if (nt < 1 || nt > kMaxNt || nx < 1 || nx > 4 * kWave) return -1;
   const int spw = (nt + kSlabWaves - 1) / kSlabWaves;
   const int xpl = (nx + kWave - 1) / kWave;
+  static const int spws[] = {1, 2, 4, 7, 8};
+  for (int i = 0; i < 5; ++i)
+    if (spw <= spws[i]) return i * 4 + (xpl - 1);
+  return -1;
+}
+
+// Host entry used by the plan: one workgroup per listed sample; every sample
+// of the launch belongs to kernel class `cls` (shapes may differ).
+int slab_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st) {
+  if (a.count == 0) return 0;
+  static const int spws[] = {1, 2, 4, 7, 8};
+  if (cls < 0 || cls >= 20) return SNAP_EUNSUPPORTED;
+  const int spw = spws[cls / 4], xpl = cls % 4 + 1;
   SlabLaunch f = mixed ? pick_slab<float>(spw, xpl) : pick_slab<double>(spw, xpl);
   if (!f) return SNAP_EUNSUPPORTED;
   f(a, st);
   return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP;
-}
-
-bool slab_supported(int nx, int nt) {
-  return nt >= 1 && nt <= kMaxNt && nx >= 1 && nx <= 4 * kWave;
 }
 
 }  // namespace snap

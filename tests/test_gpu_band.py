@@ -72,3 +72,21 @@ def test_burgers_backward(prec):
             g_o = adjoint_sample(family_of(smp), u_o, lam_o, grad[vo:vo + smp.n])
             tol = 1e-10 if prec == snap.PREC_FP64 else 1e-6
             assert rel_err(g[vo:vo + smp.n], g_o) <= tol, (flags, s, rel_err(g[vo:vo + smp.n], g_o))
+
+
+def test_burgers_full_config_sampled():
+    # the full Burgers batch (512 x 128 x 128) in the launch configuration bench.py times;
+    # the oracle checks a sample of outputs one by one
+    b = synthgen.make("burgers_lf")
+    res = gpu_project(b)
+    st = res["stats"]
+    assert (st["status"] == 0).all()
+    assert st["h_inf"].max() <= H_TOL
+    _check(b, res, [0, 255, 511], 1e-10, 1e-8)
+
+
+def test_burgers_mixed_full_config_sampled():
+    b = synthgen.make("burgers_lf")
+    res = gpu_project(b, snap.Options(precision=snap.PREC_MIXED))
+    assert (res["stats"]["status"] == 0).all()
+    _check(b, res, [3, 300], 1e-6, 1e-4)
