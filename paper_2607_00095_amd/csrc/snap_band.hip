@@ -73,6 +73,7 @@ struct BandShared {
   double Lw[kTL];          // diagonal block -> L_JJ (unit lower) with D on the diagonal
   double Xw[kTL];          // L_JJ^{-1}
   double Dv[kT];
+  double rD[kT];           // 1 / D_J
   double ring[(BB + 1) * kT];   // right-hand side / solution window of live block rows
   double newr[kT];
   double yJ[kT];
@@ -269,12 +270,12 @@ __device__ void assemble_all(const Ctx& C, const WsLayout& WL) {
 }
 
 // scatter the prefetched contributions of row a of block row I into the staging tile
-template <int BB, typename R>
+template <int BB, typename R, int NC = kContrib>
 __device__ __forceinline__ void scatter_row(int I, int a, const int* col, const double* val,
                                             R (*NR)[kTL]) {
   const int lo = (I - BB) * kT, hi = (I + 1) * kT;
 #pragma unroll
-  for (int t = 0; t < kContrib; ++t) {
+  for (int t = 0; t < NC; ++t) {
     const int cc = col[t];
     if (cc >= lo && cc < hi) {
       const int cb = cc / kT;
@@ -323,6 +324,16 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     if (t < 0) t += P;
     return J + d + t;
   };
+  // tr[s] = (I - J - d) for the block held by slot s at the current step J:
+  // 0 means the slot holds a panel block; it decreases by one per step
+  // (cyclically, period BB+1-d), so no division is needed inside the loop
+  int tr[SPW];
+#pragma unroll
+  for (int s = 0; s < SPW; ++s) tr[s] = sd[s] >= 0 ? slot_row(s, 0) - sd[s] : 0;
+  auto advance = [&]() {
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) tr[s] = tr[s] == 0 ? BB - sd[s] : tr[s] - 1;
+  };
 
   V acc[SPW];
 #pragma unroll
@@ -342,23 +353,26 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
   assemble_all<NW>(C, WL);
   const int* acol = (const int*)(C.ws + WL.acol);
   const double* aval = (const double*)(C.ws + WL.aval);
-  // prefetch registers of wavefront 1, lanes 0..15 (row `lane` of the next entering block row)
-  int pcol[kContrib];
-  double pval[kContrib];
-  double prhs = 0.0;
-  auto prefetch_row = [&](int I) {
+  // wavefront 1, lanes 0..15: row `lane` of the entering block row I, loaded
+  // while wavefront 0 factors the diagonal block (which hides the latency)
+  auto enter_row = [&](int I) {
     const int r = I * kT + lane;
     if (I < C.NB) {
+      // two halves of eight contributions bound the registers this needs
 #pragma unroll
-      for (int t = 0; t < kContrib; ++t) {
-        pcol[t] = acol[(size_t)r * kContrib + t];
-        pval[t] = aval[(size_t)r * kContrib + t];
+      for (int h = 0; h < 2; ++h) {
+        int cl[kContrib / 2];
+        double vl[kContrib / 2];
+#pragma unroll
+        for (int t = 0; t < kContrib / 2; ++t) {
+          cl[t] = acol[(size_t)r * kContrib + h * (kContrib / 2) + t];
+          vl[t] = aval[(size_t)r * kContrib + h * (kContrib / 2) + t];
+        }
+        scatter_row<BB, R, kContrib / 2>(I, lane, cl, vl, sh.NR);
       }
-      prhs = rin[r];
+      sh.newr[lane] = rin[r];
     } else {
-#pragma unroll
-      for (int t = 0; t < kContrib; ++t) { pcol[t] = -1; pval[t] = 0.0; }
-      prhs = 0.0;
+      sh.newr[lane] = 0.0;
     }
   };
   (void)rvec;
@@ -386,14 +400,13 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     lds_barrier();
   }
 
-  if (w == 1 && lane < kT) prefetch_row(BB + 1);
   int bad = 0;
   for (int J = 0; J < C.NB; ++J) {
     // (a) gather the panel column J into LDS; clear the staging area
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
       if (sd[s] < 0) continue;
-      if (slot_row(s, J) - sd[s] == J) {
+      if (tr[s] == 0) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) sh.P[sd[s]][Mfma<R>::row(lk, e) * kLd + li] = acc[s][e];
       }
@@ -403,54 +416,47 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
 
     // (b) wavefront 0: LDL^T of the diagonal block; wavefront 1: next block row
     if (w == 0) {
-      // LDL^T of the 16x16 diagonal block in LDS by one wavefront: lane owns
-      // entries (li, 4*lk + e).  Right-looking; runtime loops keep registers low.
+      // LDL^T of the 16x16 diagonal block in LDS by one wavefront, with the
+      // inverse of the unit lower factor built in the same sweep (the row
+      // operations of the elimination applied to the identity).  Lane owns
+      // entries (li, 4*lk + e) of the working matrix Lw and of X.  Pivot p reads
+      // column p of Lw (not written in step p) and row p of X (final at step p)
+      // and writes only entries of rows > p, so one wavefront sync per pivot
+      // orders everything.  D_p ends on the diagonal of Lw.
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = 4 * lk + e;
         sh.Lw[li * kLd + k] = (double)sh.P[0][li * kLd + k];
+        sh.Xw[li * kLd + k] = (li == k) ? 1.0 : 0.0;
       }
       wave_sync();
       int nonpos = 0;
       for (int p = 0; p < kT; ++p) {
         const double dp = sh.Lw[p * kLd + p];
         nonpos |= !(dp > 0.0);
-        const double lip = sh.Lw[li * kLd + p] / dp;
+        const double rdp = 1.0 / dp;
+        const double lip = (li > p) ? sh.Lw[li * kLd + p] * rdp : 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int k = 4 * lk + e;
           if (li > p && k > p) sh.Lw[li * kLd + k] -= lip * sh.Lw[k * kLd + p];
+          if (li > p && k <= p) sh.Xw[li * kLd + k] -= lip * sh.Xw[p * kLd + k];
         }
         wave_sync();
-        if (lane < kT && lane > p) sh.Lw[lane * kLd + p] = lip;
-        wave_sync();
-      }
-      // X = L_JJ^{-1} by forward elimination on the identity
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int cc = 4 * lk + e;
-        sh.Xw[li * kLd + cc] = (li == cc) ? 1.0 : 0.0;
       }
       if (lane < kT) {
-        sh.Dv[lane] = sh.Lw[lane * kLd + lane];
-        Dg[(size_t)J * kT + lane] = sh.Lw[lane * kLd + lane];
+        const double dl = sh.Lw[lane * kLd + lane];
+        sh.Dv[lane] = dl;
+        sh.rD[lane] = 1.0 / dl;
+        Dg[(size_t)J * kT + lane] = dl;
       }
       wave_sync();
-      for (int k = 0; k < kT - 1; ++k) {
-        const double lik = sh.Lw[li * kLd + k];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int cc = 4 * lk + e;
-          if (li > k && cc <= k) sh.Xw[li * kLd + cc] -= lik * sh.Xw[k * kLd + cc];
-        }
-        wave_sync();
-      }
       // T = L^{-T} D^{-1}: T[r][c] = X[c][r] / D_c ; global copy of X
       R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int cc = 4 * lk + e;
-        sh.T[li * kLd + cc] = (R)(sh.Xw[cc * kLd + li] / sh.Dv[cc]);
+        sh.T[li * kLd + cc] = (R)(sh.Xw[cc * kLd + li] * sh.rD[cc]);
         Lgd[li * kT + cc] = (R)sh.Xw[li * kLd + cc];
       }
       if (lane < kT) {
@@ -463,11 +469,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       nonpos = __any(nonpos);
       if (lane == 0 && nonpos) sh.flag[0] = 1;
     } else if (w == 1 && lane < kT) {
-      // entering block row J+BB+1 from the prefetched contributions; then
-      // prefetch the one after it
-      scatter_row<BB, R>(J + BB + 1, lane, pcol, pval, sh.NR);
-      sh.newr[lane] = prhs;
-      prefetch_row(J + BB + 2);
+      enter_row(J + BB + 1);           // entering block row J+BB+1
     }
     lds_barrier();
 
@@ -476,7 +478,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     for (int s = 0; s < SPW; ++s) {
       const int d = sd[s];
       if (d < 1) continue;
-      if (slot_row(s, J) - d != J) continue;
+      if (tr[s] != 0) continue;
       V res = V{0, 0, 0, 0};
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
@@ -508,11 +510,10 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     for (int s = 0; s < SPW; ++s) {
       const int d = sd[s];
       if (d < 0) continue;
-      const int I = slot_row(s, J), K = I - d;
-      if (K == J) {
+      if (tr[s] == 0) {
         load_nr(s, d);                       // retire panel block, take the entering one
       } else {
-        const int di = I - J, dk = K - J;    // 1 <= dk <= di <= BB
+        const int dk = tr[s], di = tr[s] + d;    // K - J and I - J: 1 <= dk <= di <= BB
         V v = acc[s];
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
@@ -526,6 +527,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       __builtin_amdgcn_sched_barrier(0);
     }
     if (threadIdx.x < kT) sh.ring[(J % (BB + 1)) * kT + threadIdx.x] = sh.newr[threadIdx.x];
+    advance();
     lds_barrier();
   }
   bad = sh.flag[0];
@@ -700,7 +702,8 @@ __device__ void to_internal(const Ctx& C, const double* canon, double* rin) {
 // mixed form.  Each sweep has a single call site.
 template <int BB, int NW, typename R>
 __device__ __attribute__((always_inline)) int solve_with_factor(
-    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, bool have_y, double* x) {
+    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, bool have_y, double* x,
+    int max_refine = 6) {
   double* Y = (double*)(C.ws + WL.Y);
   double* rin = (double*)(C.ws + WL.rin);
   double* res = (double*)(C.ws + WL.res);
@@ -713,7 +716,7 @@ __device__ __attribute__((always_inline)) int solve_with_factor(
     rn = block_max<NW>(rn, sh.red, 1);
   }
   int refines = 0;
-  for (int it = 0; it < 7; ++it) {
+  for (int it = 0; it <= max_refine; ++it) {
     if (it > 0 || !have_y) forward_sweep<BB, NW, R>(C, WL, sh, rin, Y);
     backward_sweep<BB, NW, R>(C, WL, sh, Y, it == 0 ? x : dx);
     if (it > 0) {
@@ -721,7 +724,7 @@ __device__ __attribute__((always_inline)) int solve_with_factor(
       __syncthreads();
       ++refines;
     }
-    if (plain) break;
+    if (plain || it == max_refine) break;
     const double rm = schur_residual<NW>(C, WL, x, res, sh.red);
     if (!(rm > 1e-13 * rn)) break;
     to_internal<NW>(C, res, rin);
@@ -729,12 +732,26 @@ __device__ __attribute__((always_inline)) int solve_with_factor(
   return refines;
 }
 
-// ------------------------------------------------------------------ kernel
-template <int BB, int NW, typename R, bool BWD>
-__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2))) void band_kernel(KernelArgs A) {
-  const int sid = A.order[blockIdx.x];
-  const snap_sample_desc D = A.descs[sid];
-  __shared__ BandShared<BB, NW, R> sh;
+// ------------------------------------------------------------------ kernels
+// The Newton loop is a fixed sequence of launches (init, then max_newton rounds
+// of factor / solve / step / eval, then finish), each kernel one workgroup per
+// sample.  Per-sample progress lives in the workspace header, so samples that
+// have converged (or failed) return at once from every later launch; the call
+// never synchronizes with the host.  Splitting the loop keeps each kernel's
+// live state small (the factorization's accumulator window needs most of the
+// register file).
+
+// per-sample state at the start of the sample's workspace block
+struct BandState {
+  int phase;        // 0 iterating, 1 converged and waiting for the final factor, 2 finished
+  int status;       // SNAP_ST_*
+  int iters, backtracks, refines;
+  int factor_ok;    // 1 when the stored factor was taken at the returned point
+  double mu, uscale, h1, hinf, stinf;
+};
+static_assert(sizeof(BandState) <= 256, "state must fit the header");
+
+__device__ __forceinline__ Ctx make_ctx(const KernelArgs& A, const snap_sample_desc& D, int sid, bool bwd) {
   Ctx C;
   C.nx = D.nx; C.nt = D.nt;
   C.m = D.nx * (D.nt - 1);
@@ -744,184 +761,274 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2
   C.q = 0.5 * D.dt / D.dx;
   C.c = D.p1 * D.dt / (2.0 * D.dx) + D.p0 * D.dt / (D.dx * D.dx);
   C.cd = -1.0 + 2.0 * C.c;
-  C.bwd = BWD;
+  C.bwd = bwd;
   C.uh = A.uhat ? A.uhat + D.var_off : nullptr;
   C.g = A.grad_u ? A.grad_u + D.var_off : nullptr;
   C.u = A.u + D.var_off;
   C.lam = A.lam + D.row_off;
   C.ws = A.ws + A.ws_off[sid];
+  return C;
+}
+
+#define SNAP_BAND_KERNEL __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(2, 2)))
+
+// u = u_hat, lam = 0, state reset
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_init(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ double red[NW][4];
+  const Ctx C = make_ctx(A, D, sid, false);
   const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
-  int* hdr = (int*)(C.ws + WL.hdr);
-  double* lamp = (double*)(C.ws + WL.lamp);
-  double* pv = (double*)(C.ws + WL.p);
-  const int NT = NW * kWave;
-  const bool keep = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0;
-  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
-
-  int status = SNAP_ST_MAX_ITER, iters = 0, backtracks = 0, refines = 0;
-  double hinf = 0.0, stinf = 0.0;
-
-  if constexpr (BWD) {
-    // adjoint: S b = J W^{-1} g, grad = W^{-1}(g - J^T b), at (u*, lam*)
-    double* rin = (double*)(C.ws + WL.rin);
-    double* rvec = (double*)(C.ws + WL.rvec);
-    const bool have = keep && hdr[0] == 1;
-    __syncthreads();
-    int bad = 0;
-    if (have) {
-      for (int r = threadIdx.x; r < C.M; r += NT) {
-        double v = 0.0;
-        if (r < C.m) {
-          const int k = r / C.nx, px = r - k * C.nx, x = fold_x(px, C.nx);
-          // rhs = -J W^{-1} d with d = -g
-          double s = 0.0;
-          const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
-          const double* U = C.u + (size_t)k * C.nx;
-          s += C.g[(size_t)(k + 1) * C.nx + x] / w_at(C, k + 1, x);
-          s += C.cd * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
-          s += (C.q * U[xp] - C.c) * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
-          s += (-C.q * U[xm] - C.c) * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
-          v = s;
-          rvec[(size_t)k * C.nx + x] = s;
-        }
-        rin[r] = v;
-      }
-      __syncthreads();
-    } else {
-      bad = factor_sweep<BB, NW, R>(C, WL, sh);
-    }
-    refines = solve_with_factor<BB, NW, R>(C, WL, sh, !have, lamp);
-    __syncthreads();
-    for (int v = threadIdx.x; v < C.n; v += NT) {
-      const int k = v / C.nx, x = v - k * C.nx;
-      A.grad_uhat[D.var_off + v] = (C.g[v] - jt_at(C, lamp, k, x)) / w_at(C, k, x);
-    }
-    if (threadIdx.x == 0) {
-      snap_sample_stats st;
-      st.status = bad ? SNAP_ST_SINGULAR_PIVOT : SNAP_ST_CONVERGED;
-      st.newton_iters = 0; st.ls_backtracks = 0; st.refine_steps = refines;
-      st.h_inf = 0.0; st.stat_inf = 0.0;
-      A.stats[sid] = st;
-    }
-    return;
-  } else {
-
-  // ---------------------------------------------------------------- forward
+  BandState* S = (BandState*)(C.ws + WL.hdr);
   double umax = 0.0;
   int nonfin = 0;
-  for (int v = threadIdx.x; v < C.n; v += NT) {
+  for (int v = threadIdx.x; v < C.n; v += NW * kWave) {
     const double x = C.uh[v];
     C.u[v] = x;
     umax = fmax(umax, fabs(x));
     nonfin |= !finite(x);
   }
-  for (int r = threadIdx.x; r < C.m; r += NT) C.lam[r] = 0.0;
-  if (threadIdx.x == 0) hdr[0] = 0;
-  const double uscale = 1.0 + block_max<NW>(umax, sh.red, 0);
-  if (block_max<NW>((double)nonfin, sh.red, 1) > 0.0) status = SNAP_ST_NONFINITE;
-  double mu = 0.0;
+  for (int r = threadIdx.x; r < C.m; r += NW * kWave) C.lam[r] = 0.0;
+  const double um = block_max<NW>(umax, red, 0);
+  const double nf = block_max<NW>((double)nonfin, red, 1);
+  if (threadIdx.x == 0) {
+    BandState st{};
+    st.phase = nf > 0.0 ? 2 : 0;
+    st.status = nf > 0.0 ? SNAP_ST_NONFINITE : SNAP_ST_MAX_ITER;
+    st.uscale = 1.0 + um;
+    *S = st;
+  }
+}
 
-  for (int it = 0; status != SNAP_ST_NONFINITE; ++it) {
-    // ---- evaluate h, stationarity and the objective at (u, lam)
-    double hm = 0.0, h1 = 0.0, sm = 0.0;
+// h, stationarity, convergence test at (u, lam)
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_eval(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ double red[NW][4];
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0) return;
+  const bool keep = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0;
+  double hm = 0.0, h1 = 0.0, sm = 0.0;
+  for (int v = threadIdx.x; v < C.n; v += NW * kWave) {
+    const int k = v / C.nx, x = v - k * C.nx;
+    sm = fmax(sm, fabs(dres(C, v) + jt_at(C, C.lam, k, x)));
+    if (k <= C.nt - 2) {
+      const double h = h_row(C, k, x);
+      hm = fmax(hm, fabs(h));
+      h1 += fabs(h);
+      if (!finite(h)) hm = __builtin_nan("");
+    }
+  }
+  hm = block_max<NW>(hm, red, 0);
+  sm = block_max<NW>(sm, red, 1);
+  h1 = block_sum<NW>(h1, red, 2);
+  if (threadIdx.x == 0) {
+    S->hinf = hm; S->stinf = sm; S->h1 = h1;
+    if (!finite(hm) || !finite(sm)) {
+      S->status = SNAP_ST_NONFINITE; S->phase = 2;
+    } else if (hm <= A.opt.tol_h && sm <= A.opt.tol_s * S->uscale) {
+      S->status = SNAP_ST_CONVERGED; S->phase = keep ? 1 : 2;
+    } else if (S->iters >= A.opt.max_newton) {
+      S->status = SNAP_ST_MAX_ITER; S->phase = 2;
+    }
+  }
+}
+
+// Schur factor with the fused forward substitution (also the final factor
+// at the returned point when the adjoint will need it)
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_factor(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  const int phase = S->phase;
+  if (phase == 2) return;
+  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+  __syncthreads();
+  const int bad = factor_sweep<BB, NW, R>(C, WL, sh);
+  if (threadIdx.x == 0) {
+    if (phase == 1) {
+      S->factor_ok = bad ? 0 : 1;
+      S->phase = 2;
+    } else if (bad) {
+      S->status = SNAP_ST_SINGULAR_PIVOT;
+      S->phase = 2;
+    }
+  }
+}
+
+// backward substitution (+ refinement in the mixed form): lam+ = lam + dlam
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_solve(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0) return;
+  double* lamp = (double*)(C.ws + WL.lamp);
+  // Mixed form: the Newton iteration itself corrects the float32 solve (its
+  // right-hand side h - J W^{-1} g is formed in float64 every iteration), so
+  // explicit float64 refinement is applied only in the local phase, where the
+  // float32 error would otherwise limit the last digits.
+  const int max_ref = S->hinf <= 1e-6 ? 6 : 0;
+  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, true, lamp, max_ref);
+  for (int r = threadIdx.x; r < C.m; r += NW * kWave) lamp[r] += C.lam[r];
+  if (threadIdx.x == 0) S->refines += refines;
+}
+
+// step p = -W^{-1}(u - u_hat + J^T lam+), l1-merit backtracking, update
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_step(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ double red[NW][4];
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0) return;
+  const int NT = NW * kWave;
+  const double* lamp = (const double*)(C.ws + WL.lamp);
+  double* pv = (double*)(C.ws + WL.p);
+  double dd = 0.0, pp = 0.0, lmax = 0.0;
+  for (int v = threadIdx.x; v < C.n; v += NT) {
+    const int k = v / C.nx, x = v - k * C.nx;
+    const double d = dres(C, v);
+    const double p = -(d + jt_at(C, lamp, k, x)) / w_at(C, k, x);
+    pv[v] = p;
+    dd += d * p;
+    pp += p * p;
+  }
+  for (int r = threadIdx.x; r < C.m; r += NT) lmax = fmax(lmax, fabs(lamp[r]));
+  dd = block_sum<NW>(dd, red, 0);
+  pp = block_sum<NW>(pp, red, 2);
+  lmax = block_max<NW>(lmax, red, 1);
+  const double h1 = S->h1, hinf = S->hinf;
+  const double mu = fmax(S->mu, 1.1 * lmax + 1e-8);
+  // merit phi = 1/2||u - u_hat||^2 + mu ||h||_1; its change along p is formed
+  // from differences (alpha d.p + alpha^2/2 p.p + mu (||h_t||_1 - ||h||_1)),
+  // never from phi values themselves, so rounding of the large sums cancels
+  const double dphi = dd - mu * h1;
+  double alpha = 1.0;
+  int ok = 0, backtracks = 0;
+  for (int ls = 0; ls <= A.opt.max_ls; ++ls) {
+    double ht = 0.0;
     for (int v = threadIdx.x; v < C.n; v += NT) {
       const int k = v / C.nx, x = v - k * C.nx;
-      const double d = dres(C, v);
-      sm = fmax(sm, fabs(d + jt_at(C, C.lam, k, x)));
       if (k <= C.nt - 2) {
-        const double h = h_row(C, k, x);
-        hm = fmax(hm, fabs(h));
-        h1 += fabs(h);
-        if (!finite(h)) hm = __builtin_nan("");
+        const size_t b0 = (size_t)k * C.nx;
+        const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
+        const double u0 = C.u[b0 + x] + alpha * pv[b0 + x];
+        const double up = C.u[b0 + xp] + alpha * pv[b0 + xp];
+        const double um = C.u[b0 + xm] + alpha * pv[b0 + xm];
+        const double un = C.u[b0 + C.nx + x] + alpha * pv[b0 + C.nx + x];
+        ht += fabs(un - u0 + 0.5 * C.q * (up * up - um * um) - C.c * (up - 2.0 * u0 + um));
       }
     }
-    hm = block_max<NW>(hm, sh.red, 0);
-    sm = block_max<NW>(sm, sh.red, 1);
-    h1 = block_sum<NW>(h1, sh.red, 2);
-    hinf = hm; stinf = sm;
-    if (!finite(hm) || !finite(sm)) { status = SNAP_ST_NONFINITE; break; }
-    const bool conv = hm <= A.opt.tol_h && sm <= A.opt.tol_s * uscale;
-    if (conv && !keep) { status = SNAP_ST_CONVERGED; break; }
-    if (!conv && it >= A.opt.max_newton) { status = SNAP_ST_MAX_ITER; break; }
-
-    // ---- Schur factor (at the returned point too when the adjoint needs it)
-    const int bad = factor_sweep<BB, NW, R>(C, WL, sh);
-    if (conv) {
-      status = SNAP_ST_CONVERGED;
-      if (threadIdx.x == 0) hdr[0] = bad ? 0 : 1;
-      break;
-    }
-    if (bad) { status = SNAP_ST_SINGULAR_PIVOT; break; }
-    refines += solve_with_factor<BB, NW, R>(C, WL, sh, true, lamp);
-    __syncthreads();
-    for (int r = threadIdx.x; r < C.m; r += NT) lamp[r] += C.lam[r];   // lam+ = lam + dlam
-    __syncthreads();
-
-    // ---- step p = -W^{-1}(d + J^T lam+), merit derivative
-    double dd = 0.0, pp = 0.0, lmax = 0.0;
-    for (int v = threadIdx.x; v < C.n; v += NT) {
-      const int k = v / C.nx, x = v - k * C.nx;
-      const double d = dres(C, v);
-      const double p = -(d + jt_at(C, lamp, k, x)) / w_at(C, k, x);
-      pv[v] = p;
-      dd += d * p;
-      pp += p * p;
-    }
-    for (int r = threadIdx.x; r < C.m; r += NT) lmax = fmax(lmax, fabs(lamp[r]));
-    dd = block_sum<NW>(dd, sh.red, 0);
-    pp = block_sum<NW>(pp, sh.red, 2);
-    lmax = block_max<NW>(lmax, sh.red, 1);
-    mu = fmax(mu, 1.1 * lmax + 1e-8);
-    // merit phi = 1/2||u - u_hat||^2 + mu ||h||_1; its change along p is formed
-    // from differences (alpha d.p + alpha^2/2 p.p + mu (||h_t||_1 - ||h||_1)),
-    // never from phi values themselves, so rounding of the large sums cancels
-    const double dphi = dd - mu * h1;
-
-    // ---- backtracking on the l1 merit; trial points are evaluated without
-    //      touching u (h of u + alpha p from the stencil)
-    double alpha = 1.0;
-    int ok = 0;
-    for (int ls = 0; ls <= A.opt.max_ls; ++ls) {
-      double ht = 0.0;
-      for (int v = threadIdx.x; v < C.n; v += NT) {
-        const int k = v / C.nx, x = v - k * C.nx;
-        if (k <= C.nt - 2) {
-          const size_t b0 = (size_t)k * C.nx;
-          const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
-          const double u0 = C.u[b0 + x] + alpha * pv[b0 + x];
-          const double up = C.u[b0 + xp] + alpha * pv[b0 + xp];
-          const double um = C.u[b0 + xm] + alpha * pv[b0 + xm];
-          const double un = C.u[b0 + C.nx + x] + alpha * pv[b0 + C.nx + x];
-          const double h = un - u0 + 0.5 * C.q * (up * up - um * um) - C.c * (up - 2.0 * u0 + um);
-          ht += fabs(h);
-        }
-      }
-      ht = block_sum<NW>(ht, sh.red, 1);
-      const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (ht - h1);
-      // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
-      // ||h||_1 along p sits below the rounding of the row sums
-      if (dphi_t <= 1e-4 * alpha * dphi || !(dphi < 0.0) || hinf <= 1e-6) { ok = 1; break; }
-      alpha *= 0.5;
-      ++backtracks;
-    }
-    if (!ok) { status = SNAP_ST_LS_FAIL; break; }
+    ht = block_sum<NW>(ht, red, 1);
+    const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (ht - h1);
+    // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
+    // ||h||_1 along p sits below the rounding of the row sums
+    if (dphi_t <= 1e-4 * alpha * dphi || !(dphi < 0.0) || hinf <= 1e-6) { ok = 1; break; }
+    alpha *= 0.5;
+    ++backtracks;
+  }
+  if (ok) {
     for (int v = threadIdx.x; v < C.n; v += NT) C.u[v] += alpha * pv[v];
     for (int r = threadIdx.x; r < C.m; r += NT) C.lam[r] += alpha * (lamp[r] - C.lam[r]);
-    __syncthreads();
-    ++iters;
   }
+  if (threadIdx.x == 0) {
+    S->mu = mu;
+    S->backtracks += backtracks;
+    if (ok) {
+      S->iters += 1;
+    } else {
+      S->status = SNAP_ST_LS_FAIL;
+      S->phase = 2;
+    }
+  }
+}
 
+// per-sample statistics
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_finish(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
   if (threadIdx.x == 0) {
     snap_sample_stats st;
-    st.status = status;
-    st.newton_iters = iters;
-    st.ls_backtracks = backtracks;
-    st.refine_steps = refines;
-    st.h_inf = hinf;
-    st.stat_inf = stinf;
+    st.status = S->status;
+    st.newton_iters = S->iters;
+    st.ls_backtracks = S->backtracks;
+    st.refine_steps = S->refines;
+    st.h_inf = S->hinf;
+    st.stat_inf = S->stinf;
     A.stats[sid] = st;
   }
 }
+
+// adjoint: S b = J W^{-1} g, grad = W^{-1}(g - J^T b), at (u*, lam*); reuses
+// the factor when the forward kept one at this point, else factors here
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_adjoint(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, true);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
+  double* lamp = (double*)(C.ws + WL.lamp);
+  const int NT = NW * kWave;
+  const bool keep = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0;
+  const bool have = keep && S->factor_ok == 1;
+  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+  __syncthreads();
+  int bad = 0;
+  if (have) {
+    double* rin = (double*)(C.ws + WL.rin);
+    double* rvec = (double*)(C.ws + WL.rvec);
+    for (int r = threadIdx.x; r < C.M; r += NT) {
+      double v = 0.0;
+      if (r < C.m) {
+        const int k = r / C.nx, px = r - k * C.nx, x = fold_x(px, C.nx);
+        // rhs = J W^{-1} g
+        const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
+        const double* U = C.u + (size_t)k * C.nx;
+        double s = C.g[(size_t)(k + 1) * C.nx + x] / w_at(C, k + 1, x);
+        s += C.cd * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
+        s += (C.q * U[xp] - C.c) * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
+        s += (-C.q * U[xm] - C.c) * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
+        v = s;
+        rvec[(size_t)k * C.nx + x] = s;
+      }
+      rin[r] = v;
+    }
+    __syncthreads();
+  } else {
+    bad = factor_sweep<BB, NW, R>(C, WL, sh);
+  }
+  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, !have, lamp);
+  for (int v = threadIdx.x; v < C.n; v += NT) {
+    const int k = v / C.nx, x = v - k * C.nx;
+    A.grad_uhat[D.var_off + v] = (C.g[v] - jt_at(C, lamp, k, x)) / w_at(C, k, x);
+  }
+  if (threadIdx.x == 0) {
+    snap_sample_stats st;
+    st.status = bad ? SNAP_ST_SINGULAR_PIVOT : SNAP_ST_CONVERGED;
+    st.newton_iters = 0; st.ls_backtracks = 0; st.refine_steps = refines;
+    st.h_inf = 0.0; st.stat_inf = 0.0;
+    A.stats[sid] = st;
+  }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -936,10 +1043,23 @@ static int pick_bb(int need) {
 template <int BB, typename R>
 static void launch_band(const KernelArgs& a, hipStream_t st) {
   constexpr int NW = BB <= 9 ? 4 : 8;
-  if (a.backward)
-    hipLaunchKernelGGL((band_kernel<BB, NW, R, true>), dim3(a.count), dim3(NW * kWave), 0, st, a);
-  else
-    hipLaunchKernelGGL((band_kernel<BB, NW, R, false>), dim3(a.count), dim3(NW * kWave), 0, st, a);
+  const dim3 grid(a.count), block(NW * kWave);
+  if (a.backward) {
+    hipLaunchKernelGGL((band_adjoint<BB, NW, R>), grid, block, 0, st, a);
+    return;
+  }
+  hipLaunchKernelGGL((band_init<BB, NW, R>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((band_eval<BB, NW, R>), grid, block, 0, st, a);
+  for (int it = 0; it < a.opt.max_newton; ++it) {
+    hipLaunchKernelGGL((band_factor<BB, NW, R>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((band_solve<BB, NW, R>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((band_step<BB, NW, R>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((band_eval<BB, NW, R>), grid, block, 0, st, a);
+  }
+  // the final factor of a sample that converged at the last evaluation
+  if (a.opt.flags & SNAP_FLAG_KEEP_FACTOR)
+    hipLaunchKernelGGL((band_factor<BB, NW, R>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((band_finish<BB, NW, R>), grid, block, 0, st, a);
 }
 
 template <typename R>

@@ -19,14 +19,14 @@
 // leaving a symmetric tridiagonal system in time, solved by parallel cyclic
 // reduction inside one wavefront.
 //
-// One workgroup (16 wavefronts) owns one sample for the whole Newton loop.
-// Wavefront w owns time slabs w, w+16, ...; lane l owns x = l, l+64, ...; the
+// One workgroup (8 wavefronts) owns one sample for the whole Newton loop.
+// Wavefront w owns time slabs w, w+8, ...; lane l owns x = l, l+64, ...; the
 // field stays in registers and every slab sum is a wavefront reduction.
 #include "snap_device.hpp"
 
 namespace snap {
 
-constexpr int kSlabWaves = 16;
+constexpr int kSlabWaves = 8;
 constexpr int kSlabThreads = kSlabWaves * kWave;
 constexpr int kMaxNt = 128;
 
@@ -225,7 +225,9 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
       if (k >= nt) continue;                       // uniform over the wavefront
       const double lk = (k < nr) ? sh.lam[k] : 0.0;
       const double lkm = (k >= 1) ? sh.lam[k - 1] : 0.0;
-      double S1 = 0, S2 = 0, Sd = 0, Sa2 = 0, Sa = 0, Sad = 0;
+      // a_k(x) = d row_k / d u(x,k) = a0 + 2c u(x,k) is affine in u, so four
+      // sums per slab give every slab quantity: sum u, sum u^2, sum g, sum u g
+      double Su = 0, Suu = 0, Sg = 0, Sug = 0;
 #pragma unroll
       for (int j = 0; j < XPL; ++j) {
         const int x = xof(j);
@@ -237,16 +239,18 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
           // solved for the multiplier increment with right-hand side
           // h - J W^{-1} g, which vanishes at the solution
           const double gg = d + a * lk + (k >= 1 ? lkm : 0.0) + (k == 0 ? lamic[j] : 0.0);
-          S1 += uu; S2 += uu * (1.0 - uu); Sd += gg;
-          Sa2 += a * a; Sa += a; Sad += a * gg;
+          Su += uu; Suu += uu * uu; Sg += gg; Sug += uu * gg;
           st_w = fmax(st_w, fabs(gg));
         }
       }
-      S1 = wave_sum(S1); S2 = wave_sum(S2); Sd = wave_sum(Sd);
-      Sa2 = wave_sum(Sa2); Sa = wave_sum(Sa); Sad = wave_sum(Sad);
+      Su = wave_sum(Su); Suu = wave_sum(Suu); Sg = wave_sum(Sg); Sug = wave_sum(Sug);
       if (lane == 0) {
-        sh.S1[k] = S1; sh.S2[k] = S2; sh.Sd[k] = Sd;
-        sh.Sa2[k] = Sa2; sh.Sa[k] = Sa; sh.Sad[k] = Sad;
+        const double a0 = (k < nr && f2) ? -1.0 - c : 0.0, a1 = (k < nr && f2) ? 2.0 * c : 0.0;
+        const double cnt = (double)nx;
+        sh.S1[k] = Su; sh.S2[k] = Su - Suu; sh.Sd[k] = Sg;
+        sh.Sa[k] = a0 * cnt + a1 * Su;
+        sh.Sa2[k] = a0 * a0 * cnt + 2.0 * a0 * a1 * Su + a1 * a1 * Suu;
+        sh.Sad[k] = a0 * Sg + a1 * Sug;
       }
       // one slab's reductions at a time (bounds register pressure)
       __builtin_amdgcn_sched_barrier(0);
@@ -378,13 +382,23 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
       break;
     }
 
+    // the step, once, into registers (the line search and the update reuse it)
+    double pst[SPW][XPL];
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      const int k = slab_of(s);
+#pragma unroll
+      for (int j = 0; j < XPL; ++j)
+        pst[s][j] = (k < nt && xof(j) < nx) ? step_at(s, j, k, u[s][j]) : 0.0;
+    }
+
     // merit phi = 1/2||u - u_hat||^2 + mu*||h||_1 and its directional derivative
     double lmax = 0.0;
-    for (int k = 0; k < nr; ++k) lmax = fmax(lmax, fabs(sh.lamp[k]));
     if (w == 0) {
       double lm = 0.0;
 #pragma unroll
       for (int j = 0; j < XPL; ++j) lm = fmax(lm, fabs(lampic[j]));
+      for (int k = lane; k < nr; k += kWave) lm = fmax(lm, fabs(sh.lamp[k]));
       lm = wave_max(lm);
       if (lane == 0) sh.scal[4] = lm;
     }
@@ -398,7 +412,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
         for (int j = 0; j < XPL; ++j) {
           if (xof(j) < nx) {
             const double d = u[s][j] - uhat_at(s, j);
-            const double p = step_at(s, j, k, u[s][j]);
+            const double p = pst[s][j];
             pp += p * p;
             dd += d * p;
           }
@@ -431,7 +445,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
 #pragma unroll
         for (int j = 0; j < XPL; ++j) {
           if (xof(j) < nx) {
-            const double ut = u[s][j] + alpha * step_at(s, j, k, u[s][j]);
+            const double ut = u[s][j] + alpha * pst[s][j];
             S1 += ut; S2 += ut * (1.0 - ut);
           }
         }
@@ -444,7 +458,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
 #pragma unroll
         for (int j = 0; j < XPL; ++j) {
           if (xof(j) < nx) {
-            const double ut = u[0][j] + alpha * step_at(0, j, 0, u[0][j]);
+            const double ut = u[0][j] + alpha * pst[0][j];
             hic1 += fabs(ut - gic[j]);
           }
         }
@@ -481,7 +495,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
       if (k >= nt) continue;
 #pragma unroll
       for (int j = 0; j < XPL; ++j)
-        if (xof(j) < nx) u[s][j] += alpha * step_at(s, j, k, u[s][j]);
+        if (xof(j) < nx) u[s][j] += alpha * pst[s][j];
     }
     // every thread computed its step with the old u above; now update lam, W
     lds_barrier();
@@ -534,7 +548,7 @@ using SlabLaunch = void (*)(const KernelArgs&, hipStream_t);
 
 template <int SPW, int XPL, typename TS>
 static void launch_slab(const KernelArgs& a, hipStream_t st) {
-  constexpr bool ureg = SPW * XPL <= 16;
+  constexpr bool ureg = SPW * XPL <= 26;
   hipLaunchKernelGGL((slab_kernel<SPW, XPL, ureg, TS>), dim3(a.count), dim3(kSlabThreads), 0, st, a);
 }
 
@@ -542,7 +556,7 @@ template <typename TS>
 static SlabLaunch pick_slab(int spw, int xpl) {
 #define SNAP_SLAB_CASE(S, X) if (spw <= S && xpl == X) return &launch_slab<S, X, TS>;
 #define SNAP_SLAB_ROW(X) SNAP_SLAB_CASE(1, X) SNAP_SLAB_CASE(2, X) SNAP_SLAB_CASE(4, X) \
-                         SNAP_SLAB_CASE(7, X) SNAP_SLAB_CASE(8, X)
+                         SNAP_SLAB_CASE(8, X) SNAP_SLAB_CASE(13, X) SNAP_SLAB_CASE(16, X)
   SNAP_SLAB_ROW(1) SNAP_SLAB_ROW(2) SNAP_SLAB_ROW(3) SNAP_SLAB_ROW(4)
 #undef SNAP_SLAB_ROW
 #undef SNAP_SLAB_CASE
@@ -554,8 +568,8 @@ int slab_class(int nx, int nt) {
   if (nt < 1 || nt > kMaxNt || nx < 1 || nx > 4 * kWave) return -1;
   const int spw = (nt + kSlabWaves - 1) / kSlabWaves;
   const int xpl = (nx + kWave - 1) / kWave;
-  static const int spws[] = {1, 2, 4, 7, 8};
-  for (int i = 0; i < 5; ++i)
+  static const int spws[] = {1, 2, 4, 8, 13, 16};
+  for (int i = 0; i < 6; ++i)
     if (spw <= spws[i]) return i * 4 + (xpl - 1);
   return -1;
 }
@@ -564,8 +578,8 @@ int slab_class(int nx, int nt) {
 // of the launch belongs to kernel class `cls` (shapes may differ).
 int slab_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st) {
   if (a.count == 0) return 0;
-  static const int spws[] = {1, 2, 4, 7, 8};
-  if (cls < 0 || cls >= 20) return SNAP_EUNSUPPORTED;
+  static const int spws[] = {1, 2, 4, 8, 13, 16};
+  if (cls < 0 || cls >= 24) return SNAP_EUNSUPPORTED;
   const int spw = spws[cls / 4], xpl = cls % 4 + 1;
   SlabLaunch f = mixed ? pick_slab<float>(spw, xpl) : pick_slab<double>(spw, xpl);
   if (!f) return SNAP_EUNSUPPORTED;
