@@ -85,6 +85,22 @@ __device__ __forceinline__ void lds_barrier() {
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+// 1/b from the hardware estimate refined by Newton-Raphson steps
+// (x <- x + x(1 - b x)), within about an ulp of the rounded quotient for
+// normal, finite b; a few FMAs instead of the IEEE division sequence.
+__device__ __forceinline__ double rcp_nr(double b) {
+  double x = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, x, 1.0);
+  x = __builtin_fma(x, e, x);
+  e = __builtin_fma(-b, x, 1.0);
+  return __builtin_fma(x, e, x);
+}
+__device__ __forceinline__ float rcp_nr(float b) {
+  const float x = __builtin_amdgcn_rcpf(b);
+  const float e = __builtin_fmaf(-b, x, 1.0f);
+  return __builtin_fmaf(x, e, x);
+}
+
 // Order LDS accesses of one wavefront (no cross-wave synchronization).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");

@@ -5,52 +5,74 @@
 //   SNAP_MASS_IC     rows sum_x u(.,k+1) - M0                   (k = 0..Nt-2)
 //   SNAP_FISHER_KPP  rows sum_x u(.,k+1) - sum_x u(.,k) - dt*rho*sum_x u(.,k)(1-u(.,k))
 //
-// Both are written as row_k = sum_x b*u(x,k+1) + (terms in slab k), with
-// b = 1 and a_k(x) = d row_k / d u(x,k) (0 for mass rows).  The Hessian of
-// lam^T h is diagonal and constant on a slab (2*dt*rho*lam_k on slab k), so
-// W = I + Hess(lam^T h) is one number W_k per slab.
+// Both are written as row_k = sum_x u(x,k+1) + (terms in slab k), with
+// a_k(x) = d row_k / d u(x,k) = -1 - c + 2c u(x,k), c = dt*rho (0 for mass
+// rows).  The Hessian of lam^T h is diagonal and constant on a slab
+// (2c*lam_k on slab k), so W = I + Hess(lam^T h) is one number W_k per slab.
 //
-// Schur form of the Newton-KKT system (Appendix B) with u-step
-// p = -W^{-1}(u - u_hat + J^T lam+):   S lam+ = h - J W^{-1}(u - u_hat),
-// S = J W^{-1} J^T.  With IC rows first, S = [[D, C], [C^T, T]]:
-//   D_ii = 1/W_0,   C_{i,0} = a_0(i)/W_0,
-//   T_kk = sum_x a_k^2/W_k + Nx/W_{k+1},  T_{k,k+1} = sum_x a_{k+1}/W_{k+1}.
-// Eliminating the diagonal IC block cancels the slab-0 term of T_00 exactly,
-// leaving a symmetric tridiagonal system in time, solved by parallel cyclic
-// reduction inside one wavefront.
+// Schur form of the Newton-KKT system (Appendix B): with g = u - u_hat + J^T lam
+// the stationarity residual, the multiplier increment solves
+//     S dlam = h - J W^{-1} g,   S = J W^{-1} J^T,
+// and the step is p = -W^{-1}(u - u_hat + J^T lam+), lam+ = lam + dlam.  With
+// the IC rows first, S = [[D, C], [C^T, T]] with D_ii = 1/W_0,
+// C_{i,0} = a_0(i)/W_0, T_kk = sum_x a_k^2/W_k + Nx/W_{k+1},
+// T_{k,k+1} = sum_x a_{k+1}/W_{k+1}.  Eliminating the diagonal IC block cancels
+// the slab-0 term of T_00 exactly, leaving a symmetric tridiagonal system in
+// time, solved by parallel cyclic reduction inside one wavefront.  Because
+// a_k is affine in u, four sums per slab (u, u^2, g, u*g) give every Schur
+// entry and right-hand side.
 //
-// One workgroup (8 wavefronts) owns one sample for the whole Newton loop.
-// Wavefront w owns time slabs w, w+8, ...; lane l owns x = l, l+64, ...; the
-// field stays in registers and every slab sum is a wavefront reduction.
+// Layout.  One workgroup owns one sample for the whole Newton loop.  G
+// consecutive lanes form a group that owns one time slab per round
+// (slab = group + groups*round), lane `sub` of the group owns
+// x = sub, sub+G, ...; the field u and the step p stay in registers and u_hat
+// in LDS.  A slab sum is a log2(G)-step DPP scan inside the group, so every
+// slab of a wavefront reduces at once.
+//
+// Iteration.  After wavefront 0 has solved for lam+, one pass over the field
+// forms the step p and, at the trial point u + p with multipliers lam+, all
+// four slab sums, the IC rows and the merit terms.  Wavefront 0 then decides
+// the Armijo test of the l1 merit at alpha = 1 from those sums; on acceptance
+// the same sums already describe the new iterate, so it goes straight on to
+// the convergence test and the next solve.  Two workgroup barriers per Newton
+// iteration; halving (alpha < 1) falls back to explicit trial passes.
+#include <cstdlib>
+
 #include "snap_device.hpp"
 
 namespace snap {
 
-constexpr int kSlabWaves = 8;
-constexpr int kSlabThreads = kSlabWaves * kWave;
+int slab_wide_class(int nx, int nt);
+int slab_wide_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st);
+
+namespace {
+
 constexpr int kMaxNt = 128;
+constexpr double kWFloor = 0.1;
 
 template <typename TS>
 struct PcrBuf {
-  TS a[2][kMaxNt], b[2][kMaxNt], c[2][kMaxNt], d[2][kMaxNt];
+  TS a[2][kMaxNt], b[2][kMaxNt], c[2][kMaxNt], d[2][kMaxNt], rb[2][kMaxNt];
 };
 
-// Parallel cyclic reduction of the symmetric tridiagonal system
-// diag Td[0..n), off-diagonal To[k] = T_{k,k+1}, right-hand side rhs, by ONE
-// wavefront (n <= 128, two equations per lane), in precision TS.  The result is
-// written to x (double, LDS).
+// Parallel cyclic reduction of the symmetric tridiagonal system with
+// diagonal Td[0..n), off-diagonal To[k] = T_{k,k+1} and right-hand side rhs,
+// by ONE wavefront (n <= 128, two equations per lane), in precision TS; one
+// reciprocal per equation and level.  The result is written to x (LDS).
 template <typename TS>
 __device__ void pcr_solve(int n, const double* Td, const double* To, const double* rhs,
                           double* x, PcrBuf<TS>& B) {
   const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    int j = lane + kWave * e;
+    const int j = lane + kWave * e;
     if (j < n) {
+      const TS bj = (TS)Td[j];
       B.a[0][j] = j > 0 ? (TS)To[j - 1] : (TS)0;
-      B.b[0][j] = (TS)Td[j];
+      B.b[0][j] = bj;
       B.c[0][j] = j < n - 1 ? (TS)To[j] : (TS)0;
       B.d[0][j] = (TS)rhs[j];
+      B.rb[0][j] = rcp_nr(bj);
     }
   }
   wave_sync();
@@ -59,31 +81,34 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
     TS na[2], nb[2], nc[2], nd[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      int j = lane + kWave * e;
+      const int j = lane + kWave * e;
+      TS an = 0, bj = 1, cn = 0, dj = 0;
       if (j < n) {
-        TS aj = B.a[cur][j], bj = B.b[cur][j], cj = B.c[cur][j], dj = B.d[cur][j];
-        TS an = 0, cn = 0;
+        const TS aj = B.a[cur][j], cj = B.c[cur][j];
+        bj = B.b[cur][j];
+        dj = B.d[cur][j];
         if (j - s >= 0) {
-          TS al = -aj / B.b[cur][j - s];
+          const TS al = -aj * B.rb[cur][j - s];
           an = al * B.a[cur][j - s];
           bj += al * B.c[cur][j - s];
           dj += al * B.d[cur][j - s];
         }
         if (j + s < n) {
-          TS ga = -cj / B.b[cur][j + s];
+          const TS ga = -cj * B.rb[cur][j + s];
           cn = ga * B.c[cur][j + s];
           bj += ga * B.a[cur][j + s];
           dj += ga * B.d[cur][j + s];
         }
-        na[e] = an; nb[e] = bj; nc[e] = cn; nd[e] = dj;
       }
+      na[e] = an; nb[e] = bj; nc[e] = cn; nd[e] = dj;
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      int j = lane + kWave * e;
+      const int j = lane + kWave * e;
       if (j < n) {
         B.a[cur ^ 1][j] = na[e]; B.b[cur ^ 1][j] = nb[e];
         B.c[cur ^ 1][j] = nc[e]; B.d[cur ^ 1][j] = nd[e];
+        B.rb[cur ^ 1][j] = rcp_nr(nb[e]);
       }
     }
     wave_sync();
@@ -91,447 +116,535 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   }
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    int j = lane + kWave * e;
-    if (j < n) x[j] = (double)(B.d[cur][j] / B.b[cur][j]);
+    const int j = lane + kWave * e;
+    if (j < n) x[j] = (double)(B.d[cur][j] * B.rb[cur][j]);
   }
   wave_sync();
 }
 
-struct SlabShared {
-  // per-slab sums: S1 = sum u, S2 = sum u(1-u), Sd = sum g, Sa2 = sum a^2, Sa = sum a,
-  // Sad = sum a*g with g the stationarity residual
-  double S1[kMaxNt], S2[kMaxNt], Sd[kMaxNt], Sa2[kMaxNt], Sa[kMaxNt], Sad[kMaxNt];
-  double W[kMaxNt];      // W_k per slab
-  double lam[kMaxNt];    // current multipliers of the slab rows
-  double lamp[kMaxNt];   // Newton multipliers lam+
-  double Td[kMaxNt], To[kMaxNt], r[kMaxNt], res[kMaxNt], dx[kMaxNt];
-  double red[kSlabWaves][4];
-  double scal[16];
-  int flag[4];
-};
-
-// Row-k coefficient on slab k (derivative of row k w.r.t. u(x,k)).
-__device__ __forceinline__ double coef_a(bool f2, double c, double uu) {
-  return f2 ? (-1.0 - c * (1.0 - 2.0 * uu)) : 0.0;
+// Sum over each aligned group of G lanes (G a power of two <= 64): an
+// inclusive DPP scan (row_shr 1/2/4/8 inside rows of 16 lanes, then
+// row_bcast 15/31 across rows).  The LAST lane of every group ends holding
+// its group's total; other lanes hold partial sums.  Every lane of the
+// wavefront must be active.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_d<0x111, 0xf, true>(v);
+  if constexpr (G >= 4) v += dpp_d<0x112, 0xf, true>(v);
+  if constexpr (G >= 8) v += dpp_d<0x114, 0xf, true>(v);
+  if constexpr (G >= 16) v += dpp_d<0x118, 0xf, true>(v);
+  if constexpr (G >= 32) v += dpp_d<0x142, 0xa, false>(v);
+  if constexpr (G >= 64) v += dpp_d<0x143, 0xc, false>(v);
+  return v;
 }
 
-template <int SPW, int XPL, bool UREG, typename TS>
-__global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
+// group maximum of non-negative values (same scan, fmax)
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+  if constexpr (G >= 2) v = fmax(v, dpp_d<0x111, 0xf, true>(v));
+  if constexpr (G >= 4) v = fmax(v, dpp_d<0x112, 0xf, true>(v));
+  if constexpr (G >= 8) v = fmax(v, dpp_d<0x114, 0xf, true>(v));
+  if constexpr (G >= 16) v = fmax(v, dpp_d<0x118, 0xf, true>(v));
+  if constexpr (G >= 32) v = fmax(v, dpp_d<0x142, 0xa, false>(v));
+  if constexpr (G >= 64) v = fmax(v, dpp_d<0x143, 0xc, false>(v));
+  return v;
+}
+
+template <int NXM>
+struct SlabSh {
+  // per-slab sums at the current (or trial) point: S1 = sum u, S2 = sum u(1-u),
+  // Sd = sum g, and the Schur quantities Sa = sum a, Sa2 = sum a^2, Sad = sum a g
+  double S1[kMaxNt], S2[kMaxNt], Sd[kMaxNt], Sa[kMaxNt], Sa2[kMaxNt], Sad[kMaxNt];
+  double W[kMaxNt];      // W_k per slab at the current point
+  double rW[kMaxNt];     // 1/W_k
+  double lam[kMaxNt];    // multipliers of the slab rows at the current point
+  double lamp[kMaxNt];   // lam+ of the pending step
+  double Td[kMaxNt], To[kMaxNt], r[kMaxNt], res[kMaxNt], dx[kMaxNt];
+  double lamic[NXM], lampic[NXM], ric[NXM], gic[NXM];   // IC rows
+  double red[16][4];     // per-wavefront partials: max|g|, p.p, (u-u_hat).p
+  double scal[4];        // IC rows: sum a_0 r_ic, max|h_ic|, sum|h_ic|
+  int flag[4];           // done, accepted, backtrack, line-search verdict
+};
+
+// The kernel's LDS in one object, the large u_hat staging last, so that every
+// small array sits below 64 KiB and is reached with immediate offsets.
+template <int NXM, int UHN, typename TS>
+struct SlabLds {
+  SlabSh<NXM> sh;
+  PcrBuf<TS> pcr;
+  double uhl[UHN];   // u_hat (forward) or u* + grad_u (adjoint)
+};
+
+template <int NW, int G, int XPL, int RMAX, int UHN, typename TS>
+__global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
+  constexpr int NT = NW * kWave;   // threads
+  constexpr int NG = NT / G;       // slab groups per round
+  constexpr int GPW = kWave / G;   // groups per wavefront
+  constexpr int NXM = G * XPL;     // widest grid of the class
+  static_assert(NW <= 16 && G <= kWave && NG * RMAX <= kMaxNt, "slab class");
+
   const int sid = A.order[blockIdx.x];
   const snap_sample_desc D = A.descs[sid];
   const int nx = D.nx, nt = D.nt, nr = nt - 1;
   const bool f2 = (D.family == SNAP_FISHER_KPP);
   const double c = f2 ? D.dt * D.p0 : 0.0;
-  const double wfloor = 0.1;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // wave-uniform
+  const double a0c = f2 ? -1.0 - c : 0.0, a1c = f2 ? 2.0 * c : 0.0;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);   // wave-uniform
+  const int grp = tid / G, sub = tid & (G - 1);
+  const bool glast = sub == G - 1;
   const bool bwd = A.backward != 0;
+  const int64_t vo = D.var_off;
 
-  __shared__ SlabShared sh;
-  __shared__ PcrBuf<TS> pcr;
+  __shared__ SlabLds<NXM, UHN, TS> lds;
+  SlabSh<NXM>& sh = lds.sh;
+  PcrBuf<TS>& pcr = lds.pcr;
+  double* const uhl = lds.uhl;
 
-  const double* uhat_g = A.uhat + D.var_off;
   const double* aux = A.aux + D.aux_off;
   const double m0 = f2 ? 0.0 : aux[nx];
 
-  double u[SPW][XPL];
-  double uh[UREG ? SPW : 1][UREG ? XPL : 1];
-  double gic[XPL], lamic[XPL], lampic[XPL];
-
-  auto slab_of = [&](int s) { return w + kSlabWaves * s; };
-  auto xof = [&](int j) { return lane + kWave * j; };
-  // u_hat as seen by the step: forward -> input u_hat; backward -> u* + grad_u,
-  // so that u - u_hat_eff = -grad_u and the step formula yields the adjoint.
-  auto uhat_at = [&](int s, int j) -> double {
-    if constexpr (UREG) {
-      return uh[s][j];
-    } else {
-      int64_t idx = (int64_t)slab_of(s) * nx + xof(j);
-      return bwd ? (A.u[D.var_off + idx] + A.grad_u[D.var_off + idx]) : uhat_g[idx];
-    }
+  auto slab = [&](int r) { return grp + NG * r; };
+  auto xat = [&](int j) { return sub + G * j; };
+  // element (round r, j) sits at k*nx + x = base + r*rstride + G*j
+  const int base = grp * nx + sub;
+  const int rstride = __builtin_amdgcn_readfirstlane(NG * nx);
+  auto eidx_from = [&](int b, int r, int j) { return b + r * rstride + G * j; };
+  auto eidx = [&](int r, int j) { return eidx_from(base, r, j); };
+  // The Newton loop re-reads u_hat and the IC targets from LDS in every pass;
+  // an opaque copy of the lane's base index keeps the compiler from hoisting
+  // those loop-invariant reads into registers (which would not fit).
+  auto opaque = [](int v) {
+    asm volatile("" : "+v"(v));
+    return v;
   };
+  // wavefront w holds a slab < nt in round r (uniform over the wavefront)
+  auto live = [&](int r) { return w * GPW + NG * r < nt; };
+  auto coef = [&](int k, double uu) { return k < nr ? a0c + a1c * uu : 0.0; };
+  auto wslab = [&](int k, double l) { return k < nr ? fmax(1.0 + 2.0 * c * l, kWFloor) : 1.0; };
+
+  double u[RMAX][XPL], pst[RMAX][XPL];
 
   // ---------------------------------------------------------------- load
   double umax = 0.0;
   bool nonfinite = false;
+  // every load is issued before the first use (indices clamped, no branches);
+  // the adjoint reads u* into u and grad_u into pst
+  {
+    const double* src = bwd ? A.u + vo : A.uhat + vo;
 #pragma unroll
-  for (int s = 0; s < SPW; ++s) {
-    const int k = slab_of(s);
+    for (int r = 0; r < RMAX; ++r)
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) {
+        const bool ok = slab(r) < nt && xat(j) < nx;
+        const int idx = ok ? eidx(r, j) : 0;
+        u[r][j] = src[idx];
+        pst[r][j] = bwd ? A.grad_u[vo + idx] : 0.0;
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    const int k = slab(r);
 #pragma unroll
     for (int j = 0; j < XPL; ++j) {
-      const int x = xof(j);
-      double uu = 0.0, hh = 0.0;
-      if (k < nt && x < nx) {
-        int64_t idx = (int64_t)k * nx + x;
-        if (bwd) {
-          uu = A.u[D.var_off + idx];
-          hh = uu + A.grad_u[D.var_off + idx];
-        } else {
-          hh = uhat_g[idx];
-          uu = hh;
-        }
-        umax = fmax(umax, fabs(hh));
-        nonfinite |= !finite(hh) || !finite(uu);
-      }
-      u[s][j] = uu;
-      if constexpr (UREG) uh[s][j] = hh;
+      const bool ok = k < nt && xat(j) < nx;
+      const double uu = ok ? u[r][j] : 0.0;
+      const double hh = ok ? uu + pst[r][j] : 0.0;   // u_hat, or u* + grad_u
+      u[r][j] = uu;
+      pst[r][j] = 0.0;
+      if (ok) uhl[eidx(r, j)] = hh;
+      umax = fmax(umax, fabs(hh));
+      nonfinite |= !finite(hh) || !finite(uu);
     }
   }
-#pragma unroll
-  for (int j = 0; j < XPL; ++j) {
-    const int x = xof(j);
-    gic[j] = (w == 0 && x < nx) ? aux[x] : 0.0;
-    lamic[j] = (bwd && w == 0 && x < nx) ? A.lam[D.row_off + x] : 0.0;
-    lampic[j] = 0.0;
+  for (int x = tid; x < nx; x += NT) {
+    sh.gic[x] = aux[x];
+    sh.lamic[x] = 0.0;
+    sh.lampic[x] = 0.0;
   }
-  for (int k = threadIdx.x; k < kMaxNt; k += kSlabThreads) {
-    double l = (bwd && k < nr) ? A.lam[D.row_off + nx + k] : 0.0;
-    sh.lam[k] = l;
+  // the adjoint takes W at lam*, and its right-hand side J W^{-1} grad_u only,
+  // so the multipliers entering the stationarity residual are zero
+  for (int k = tid; k < kMaxNt; k += NT) {
+    const double l = (bwd && k < nr) ? A.lam[D.row_off + nx + k] : 0.0;
+    const double wk = wslab(k, l);
+    sh.W[k] = wk;
+    sh.rW[k] = rcp_nr(wk);
+    sh.lam[k] = 0.0;
     sh.lamp[k] = 0.0;
-    double wk = (k < nr) ? 1.0 + 2.0 * c * l : 1.0;
-    sh.W[k] = fmax(wk, wfloor);
-  }
-  if (bwd) {
-    // W is taken at lam*; the adjoint right-hand side uses J W^{-1} grad_u only,
-    // so the multipliers entering the stationarity residual are zero
-    lds_barrier();
-    for (int k = threadIdx.x; k < kMaxNt; k += kSlabThreads) sh.lam[k] = 0.0;
-#pragma unroll
-    for (int j = 0; j < XPL; ++j) lamic[j] = 0.0;
   }
   {
-    double mx = wave_max(umax);
-    int nf = __any(nonfinite) ? 1 : 0;
+    const double mx = wave_max(umax);
+    const int nf = __any(nonfinite) ? 1 : 0;
     if (lane == 0) { sh.red[w][0] = mx; sh.red[w][1] = (double)nf; }
   }
   lds_barrier();
   double uscale = 0.0, nfin = 0.0;
-  for (int q = 0; q < kSlabWaves; ++q) { uscale = fmax(uscale, sh.red[q][0]); nfin += sh.red[q][1]; }
+  for (int q = 0; q < NW; ++q) { uscale = fmax(uscale, sh.red[q][0]); nfin += sh.red[q][1]; }
   uscale += 1.0;
   lds_barrier();
 
-  double mu = 0.0;
-  int iters = 0, backtracks = 0, refines = 0, status = SNAP_ST_MAX_ITER;
-  double hinf = 0.0, stinf = 0.0;
-  if (nfin > 0.0) status = SNAP_ST_NONFINITE;
-  const int max_it = bwd ? 1 : A.opt.max_newton;
-
-  for (int it = 0; status != SNAP_ST_NONFINITE; ++it) {
-    // ------------------------------------------------ pass 1: slab sums
-    double st_w = 0.0;
+  // Slab sums at the point u + alpha*p with multipliers lamv (slab rows) and
+  // lamicv (IC rows): sum u, sum u^2, sum g, sum u g per slab, and the IC
+  // rows' r_ic = h_ic - g/W_0 (W_0 of those multipliers).  With STEP the
+  // step p is first formed at the current point with lam+ (into pst), and
+  // the merit terms p.p and (u - u_hat).p are accumulated.
+  auto sums_pass = [&](const double* lamv, const double* lamicv, bool step) {
+    const int eb = opaque(base), xs = opaque(sub), gq = opaque(grp);
+    double st = 0.0, pp = 0.0, dd = 0.0;
+    // W_0 at the point the sums describe: of lam+ at a trial point, else the
+    // stored one (the adjoint keeps W of lam* while its multipliers are zero)
+    const double rW0 = step ? rcp_nr(wslab(0, nr > 0 ? lamv[0] : 0.0)) : sh.rW[0];
 #pragma unroll
-    for (int s = 0; s < SPW; ++s) {
-      const int k = slab_of(s);
-      if (k >= nt) continue;                       // uniform over the wavefront
-      const double lk = (k < nr) ? sh.lam[k] : 0.0;
-      const double lkm = (k >= 1) ? sh.lam[k - 1] : 0.0;
-      // a_k(x) = d row_k / d u(x,k) = a0 + 2c u(x,k) is affine in u, so four
-      // sums per slab give every slab quantity: sum u, sum u^2, sum g, sum u g
-      double Su = 0, Suu = 0, Sg = 0, Sug = 0;
+    for (int r = 0; r < RMAX; ++r) {
+      if (!live(r)) continue;
+      const int k = gq + NG * r;
+      const bool kv = k < nt;
+      const bool law = k < nr;
+      // per-slab constants: a = a0 + a1 u on law slabs (0 on the last slab);
+      // the +1 coefficient of row k-1 on slab k, or the IC multiplier on slab 0
+      const double a0 = law ? a0c : 0.0, a1 = law ? a1c : 0.0;
+      const double lk = law ? lamv[k] : 0.0;
+      const double lkm = (k >= 1 && kv) ? lamv[k - 1] : 0.0;
+      const bool ic = r == 0 && k == 0;
+      // step at the current point: W of the current multipliers
+      const double rWc = kv ? sh.rW[k] : 1.0;
+      double Su = 0, Suu = 0, Sg = 0, Sug = 0, sar = 0, hmx = 0, h1 = 0;
 #pragma unroll
       for (int j = 0; j < XPL; ++j) {
-        const int x = xof(j);
-        if (x < nx) {
-          const double uu = u[s][j];
-          const double d = uu - uhat_at(s, j);
-          const double a = (k < nr) ? coef_a(f2, c, uu) : 0.0;
-          // stationarity residual g = u - u_hat + J^T lam; the Newton system is
-          // solved for the multiplier increment with right-hand side
-          // h - J W^{-1} g, which vanishes at the solution
-          const double gg = d + a * lk + (k >= 1 ? lkm : 0.0) + (k == 0 ? lamic[j] : 0.0);
-          Su += uu; Suu += uu * uu; Sg += gg; Sug += uu * gg;
-          st_w = fmax(st_w, fabs(gg));
+        const int x = xat(j);
+        if (kv && x < nx) {
+          double uu = u[r][j];
+          const double uh = uhl[eb + r * rstride + G * j];
+          const double lm = ic ? lamicv[xs + G * j] : lkm;
+          if (step) {
+            const double d = uu - uh;
+            const double jt = d + (a0 + a1 * uu) * lk + lm;
+            const double p = -jt * rWc;
+            pst[r][j] = p;
+            pp += p * p;
+            dd += d * p;
+            uu = uu + 1.0 * p;
+          }
+          const double a = a0 + a1 * uu;
+          const double g = (uu - uh) + a * lk + lm;
+          Su += uu; Suu += uu * uu; Sg += g; Sug += uu * g;
+          st = fmax(st, fabs(g));
+          if (ic) {
+            const double hic = bwd ? 0.0 : uu - sh.gic[xs + G * j];
+            const double ric = hic - g * rW0;
+            sh.ric[xs + G * j] = ric;
+            sar += a * ric;
+            hmx = fmax(hmx, fabs(hic));
+            h1 += fabs(hic);
+          }
         }
       }
-      Su = wave_sum(Su); Suu = wave_sum(Suu); Sg = wave_sum(Sg); Sug = wave_sum(Sug);
-      if (lane == 0) {
-        const double a0 = (k < nr && f2) ? -1.0 - c : 0.0, a1 = (k < nr && f2) ? 2.0 * c : 0.0;
+      Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
+      Sg = group_sum<G>(Sg); Sug = group_sum<G>(Sug);
+      if (glast && kv) {
         const double cnt = (double)nx;
         sh.S1[k] = Su; sh.S2[k] = Su - Suu; sh.Sd[k] = Sg;
         sh.Sa[k] = a0 * cnt + a1 * Su;
         sh.Sa2[k] = a0 * a0 * cnt + 2.0 * a0 * a1 * Su + a1 * a1 * Suu;
         sh.Sad[k] = a0 * Sg + a1 * Sug;
       }
-      // one slab's reductions at a time (bounds register pressure)
+      if (w == 0 && r == 0) {   // group 0 holds slab 0 and the IC rows
+        sar = group_sum<G>(sar); h1 = group_sum<G>(h1); hmx = group_max<G>(hmx);
+        if (lane == G - 1) { sh.scal[0] = sar; sh.scal[1] = hmx; sh.scal[2] = h1; }
+      }
+      // one round at a time: bounds the values in flight
       __builtin_amdgcn_sched_barrier(0);
     }
-    // IC rows live on slab 0, owned by wavefront 0 (s = 0)
-    double ric[XPL];
+    st = wave_max(st);
+    if (step) { pp = wave_sum(pp); dd = wave_sum(dd); }
+    if (lane == 0) { sh.red[w][0] = st; sh.red[w][1] = pp; sh.red[w][2] = dd; }
+  };
+
+  // feasibility row k from the slab sums S1, S2
+  auto row_h = [&](int k) -> double {
+    return f2 ? sh.S1[k + 1] - sh.S1[k] - c * sh.S2[k] : sh.S1[k + 1] - m0;
+  };
+  // sum of |h| over all rows (IC rows from scal[2]); wavefront 0 only
+  auto h1_rows = [&]() -> double {
+    double h1 = (lane == 0) ? sh.scal[2] : 0.0;
+    for (int k = lane; k < nr; k += kWave) h1 += fabs(row_h(k));
+    return wave_sum(h1);
+  };
+
+  double mu = 0.0, hinf = 0.0, stinf = 0.0, h1cur = 0.0;
+  int iters = 0, backtracks = 0, refines = 0, status = SNAP_ST_MAX_ITER;
+  if (nfin > 0.0) status = SNAP_ST_NONFINITE;
+  const int max_it = bwd ? 1 : A.opt.max_newton;
+  bool pend = false;   // the sums describe the trial point u + p of a pending step
+
+  if (status != SNAP_ST_NONFINITE) {
+    sums_pass(sh.lam, sh.lamic, false);
+    lds_barrier();
+  }
+
+  for (int it = 0; status != SNAP_ST_NONFINITE; ++it) {
+    // ------------------------------------------------ wavefront 0: accept, test, solve
     if (w == 0) {
-      double sar = 0.0, hicmax = 0.0, hic1 = 0.0;
-      const double W0 = sh.W[0];
+      int done = 0, acc = 0, bt = 0;
+      // rows k = lane and lane + 64 (nr <= 127): h from the slab sums, once
+      double hk[2];
 #pragma unroll
-      for (int j = 0; j < XPL; ++j) {
-        const int x = xof(j);
-        ric[j] = 0.0;
-        if (x < nx) {
-          const double uu = u[0][j];
-          const double a0 = (nr > 0) ? coef_a(f2, c, uu) : 0.0;
-          const double gg = uu - uhat_at(0, j) + lamic[j] + (nr > 0 ? a0 * sh.lam[0] : 0.0);
-          const double hic = bwd ? 0.0 : uu - gic[j];
-          ric[j] = hic - gg / W0;
-          sar += a0 * ric[j];
-          hicmax = fmax(hicmax, fabs(hic));
-          hic1 += fabs(hic);
+      for (int e = 0; e < 2; ++e) {
+        const int k = lane + kWave * e;
+        hk[e] = (k < nr && !bwd) ? row_h(k) : 0.0;
+      }
+      double h1 = (lane == 0) ? sh.scal[2] : 0.0;
+      h1 += fabs(hk[0]) + fabs(hk[1]);
+      h1 = wave_sum(h1);
+      if (pend) {
+        // Armijo test of phi = 1/2||u - u_hat||^2 + mu||h||_1 at alpha = 1; the
+        // change is formed from differences, d.p + p.p/2 + mu(||h_t||_1 - ||h||_1),
+        // so rounding of the large sums in phi never decides.  Local phase
+        // (||h||_inf <= 1e-6): full Newton steps.
+        double pp = 0.0, dd = 0.0;
+        for (int q = 0; q < NW; ++q) { pp += sh.red[q][1]; dd += sh.red[q][2]; }
+        const double dphi = dd - mu * h1cur;
+        const double dphit = dd + 0.5 * pp + mu * (h1 - h1cur);
+        acc = (dphit <= 1e-4 * dphi) || !(dphi < 0.0) || hinf <= 1e-6;
+        if (acc) {
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r)
+#pragma unroll
+            for (int j = 0; j < XPL; ++j) u[r][j] += 1.0 * pst[r][j];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int k = lane + kWave * e;
+            if (k < nr) {
+              const double l = sh.lamp[k];
+              const double wk = wslab(k, l);
+              sh.lam[k] = l;
+              sh.W[k] = wk;
+              sh.rW[k] = rcp_nr(wk);
+            }
+          }
+          for (int x = lane; x < nx; x += kWave) sh.lamic[x] = sh.lampic[x];
+          wave_sync();
+        } else {
+          bt = 1;
         }
       }
-      sar = wave_sum(sar); hicmax = wave_max(hicmax); hic1 = wave_sum(hic1);
-      if (lane == 0) { sh.scal[0] = sar; sh.scal[1] = hicmax; sh.scal[2] = hic1; }
-    }
-    st_w = wave_max(st_w);
-    if (lane == 0) sh.red[w][0] = st_w;
-    lds_barrier();
-
-    // ------------------------------------------------ wavefront 0: rows, test, solve
-    if (w == 0) {
-      double hmax = sh.scal[1], h1 = sh.scal[2];
-      for (int k = lane; k < nr; k += kWave) {
-        double hk = bwd ? 0.0
-                        : (f2 ? sh.S1[k + 1] - sh.S1[k] - c * sh.S2[k] : sh.S1[k + 1] - m0);
-        const double Wk = sh.W[k], Wk1 = sh.W[k + 1];
-        double rk = hk - (sh.Sad[k] / Wk + sh.Sd[k + 1] / Wk1);
-        if (k == 0) rk -= sh.scal[0];
-        sh.r[k] = rk;
-        sh.Td[k] = (k == 0 ? 0.0 : sh.Sa2[k] / Wk) + (double)nx / Wk1;
-        sh.To[k] = (k + 1 < nr) ? sh.Sa[k + 1] / Wk1 : 0.0;
-        hmax = fmax(hmax, fabs(hk));
-        h1 += fabs(hk);
-        if (!finite(hk)) hmax = __builtin_nan("");
-      }
-      hmax = wave_max(hmax);
-      h1 = wave_sum(h1);
-      double stmax = 0.0;
-      for (int q = 0; q < kSlabWaves; ++q) stmax = fmax(stmax, sh.red[q][0]);
-      int done = 0;
-      if (!bwd) {
-        hinf = hmax; stinf = stmax;
-        if (!finite(hmax) || !finite(stmax)) done = 2;
-        else if (hmax <= A.opt.tol_h && stmax <= A.opt.tol_s * uscale) done = 1;
-        else if (it >= max_it) done = 3;
-      }
-      if (lane == 0) { sh.flag[0] = done; sh.scal[3] = h1; }
-      if (!done && nr > 0) {
-        if constexpr (sizeof(TS) == sizeof(double)) {
-          pcr_solve<TS>(nr, sh.Td, sh.To, sh.r, sh.lamp, pcr);
-        } else {
-          // float32 solve + float64 residual refinement
-          pcr_solve<TS>(nr, sh.Td, sh.To, sh.r, sh.lamp, pcr);
-          double rn = 0.0;
-          for (int k = lane; k < nr; k += kWave) rn = fmax(rn, fabs(sh.r[k]));
-          rn = wave_max(rn);
-          for (int ref = 0; ref < 4; ++ref) {
-            double resmax = 0.0;
-            for (int k = lane; k < nr; k += kWave) {
-              double tx = sh.Td[k] * sh.lamp[k];
-              if (k > 0) tx += sh.To[k - 1] * sh.lamp[k - 1];
-              if (k + 1 < nr) tx += sh.To[k] * sh.lamp[k + 1];
-              sh.res[k] = sh.r[k] - tx;
-              resmax = fmax(resmax, fabs(sh.res[k]));
-            }
-            resmax = wave_max(resmax);
-            wave_sync();
-            if (!(resmax > 1e-15 * rn)) break;
-            pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
-            for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.dx[k];
-            wave_sync();
-            ++refines;
+      if (!bt) {
+        double hmax = (lane == 0) ? sh.scal[1] : 0.0;
+        bool nf = false;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int k = lane + kWave * e;
+          if (k < nr) {
+            const double rWk = sh.rW[k], rWk1 = sh.rW[k + 1];
+            double rk = hk[e] - (sh.Sad[k] * rWk + sh.Sd[k + 1] * rWk1);
+            if (k == 0) rk -= sh.scal[0];
+            sh.r[k] = rk;
+            sh.Td[k] = (k == 0 ? 0.0 : sh.Sa2[k] * rWk) + (double)nx * rWk1;
+            sh.To[k] = (k + 1 < nr) ? sh.Sa[k + 1] * rWk1 : 0.0;
+            hmax = fmax(hmax, fabs(hk[e]));
+            nf |= !finite(hk[e]);
           }
         }
-      }
-      if (!done) {
-        // sh.lamp holds the increment; form lam+ = lam + dlam
-        const double l0 = nr > 0 ? sh.lamp[0] : 0.0;
-        const double W0 = sh.W[0];
-#pragma unroll
-        for (int j = 0; j < XPL; ++j) {
-          const double a0 = (nr > 0) ? coef_a(f2, c, u[0][j]) : 0.0;
-          lampic[j] = lamic[j] + (W0 * ric[j] - a0 * l0);
+        hmax = wave_max(hmax);
+        nf = __any(nf);
+        double stmax = 0.0;
+        for (int q = 0; q < NW; ++q) stmax = fmax(stmax, sh.red[q][0]);
+        if (!bwd) {
+          hinf = hmax; stinf = stmax; h1cur = h1;
+          if (nf || !finite(hmax) || !finite(stmax)) done = 2;
+          else if (hmax <= A.opt.tol_h && stmax <= A.opt.tol_s * uscale) done = 1;
+          else if (it >= max_it) done = 3;
         }
         wave_sync();
-        for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.lam[k];
+        if (!done && nr > 0) {
+          pcr_solve<TS>(nr, sh.Td, sh.To, sh.r, sh.lamp, pcr);
+          if constexpr (sizeof(TS) != sizeof(double)) {
+            // float32 solve, float64 residual and refinement
+            constexpr int max_ref = 4;
+            double rn = 0.0;
+            for (int k = lane; k < nr; k += kWave) rn = fmax(rn, fabs(sh.r[k]));
+            rn = wave_max(rn);
+            for (int ref = 0; ref < max_ref; ++ref) {
+              double resmax = 0.0;
+              for (int k = lane; k < nr; k += kWave) {
+                double tx = sh.Td[k] * sh.lamp[k];
+                if (k > 0) tx += sh.To[k - 1] * sh.lamp[k - 1];
+                if (k + 1 < nr) tx += sh.To[k] * sh.lamp[k + 1];
+                sh.res[k] = sh.r[k] - tx;
+                resmax = fmax(resmax, fabs(sh.res[k]));
+              }
+              resmax = wave_max(resmax);
+              wave_sync();
+              if (!(resmax > 1e-15 * rn)) break;
+              pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
+              for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.dx[k];
+              wave_sync();
+              ++refines;
+            }
+          }
+        }
+        if (!done) {
+          // sh.lamp holds dlam; IC multipliers from the eliminated block, then
+          // lam+ = lam + dlam, and the penalty mu >= 1.1 ||lam+||_inf
+          const double l0 = nr > 0 ? sh.lamp[0] : 0.0;
+          const double W0 = sh.W[0];
+          double lm = 0.0;
+          if (grp == 0) {
+#pragma unroll
+            for (int j = 0; j < XPL; ++j) {
+              const int x = xat(j);
+              if (x < nx) {
+                const double lpi = sh.lamic[x] + (W0 * sh.ric[x] - coef(0, u[0][j]) * l0);
+                sh.lampic[x] = lpi;
+                lm = fmax(lm, fabs(lpi));
+              }
+            }
+          }
+          wave_sync();
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int k = lane + kWave * e;
+            if (k < nr) {
+              const double l = sh.lamp[k] + sh.lam[k];
+              sh.lamp[k] = l;
+              lm = fmax(lm, fabs(l));
+            }
+          }
+          lm = wave_max(lm);
+          mu = fmax(mu, 1.1 * lm + 1e-8);
+        }
       }
+      if (lane == 0) { sh.flag[0] = done; sh.flag[1] = acc; sh.flag[2] = bt; }
     }
     lds_barrier();
-    const int done = sh.flag[0];
+    const int done = sh.flag[0], acc = sh.flag[1], bt = sh.flag[2];
+    if (acc) {
+      if (w != 0) {
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+#pragma unroll
+          for (int j = 0; j < XPL; ++j) u[r][j] += 1.0 * pst[r][j];
+      }
+      ++iters;
+    }
+    if (bt) {
+      // ---------------------------------------------- backtracking (alpha < 1)
+      double alpha = 1.0;
+      int ok = 0;
+      ++backtracks;
+      for (int ls = 1; ls <= A.opt.max_ls; ++ls) {
+        alpha *= 0.5;
+        const int xs = opaque(sub), gq = opaque(grp);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+          if (!live(r)) continue;
+          const int k = gq + NG * r;
+          double Su = 0, Suu = 0, h1 = 0;
+#pragma unroll
+          for (int j = 0; j < XPL; ++j) {
+            const int x = xat(j);
+            if (k < nt && x < nx) {
+              const double ut = u[r][j] + alpha * pst[r][j];
+              Su += ut; Suu += ut * ut;
+              if (r == 0 && k == 0) h1 += fabs(ut - sh.gic[xs + G * j]);
+            }
+          }
+          Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
+          if (glast && k < nt) { sh.S1[k] = Su; sh.S2[k] = Su - Suu; }
+          if (w == 0 && r == 0) {
+            h1 = group_sum<G>(h1);
+            if (lane == G - 1) sh.scal[2] = h1;
+          }
+        }
+        lds_barrier();
+        if (w == 0) {
+          double pp = 0.0, dd = 0.0;
+          for (int q = 0; q < NW; ++q) { pp += sh.red[q][1]; dd += sh.red[q][2]; }
+          const double dphi = dd - mu * h1cur;
+          const double dphit = alpha * dd + 0.5 * alpha * alpha * pp + mu * (h1_rows() - h1cur);
+          const int good = (dphit <= 1e-4 * alpha * dphi) || !(dphi < 0.0) ? 1 : 0;
+          if (lane == 0) sh.flag[3] = good;
+        }
+        lds_barrier();
+        if (sh.flag[3]) { ok = 1; break; }
+        ++backtracks;
+      }
+      if (!ok) {
+        status = SNAP_ST_LS_FAIL;
+        break;
+      }
+      // accept: u += alpha p, lam += alpha (lam+ - lam); fresh sums at the new point
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r)
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) u[r][j] += alpha * pst[r][j];
+      for (int k = tid; k < nr; k += NT) {
+        const double l = sh.lam[k] + alpha * (sh.lamp[k] - sh.lam[k]);
+        const double wk = wslab(k, l);
+        sh.lam[k] = l;
+        sh.W[k] = wk;
+        sh.rW[k] = rcp_nr(wk);
+      }
+      for (int x = tid; x < nx; x += NT) sh.lamic[x] += alpha * (sh.lampic[x] - sh.lamic[x]);
+      ++iters;
+      lds_barrier();
+      sums_pass(sh.lam, sh.lamic, false);
+      lds_barrier();
+      pend = false;
+      continue;
+    }
     if (done) {
       status = done == 1 ? SNAP_ST_CONVERGED : (done == 2 ? SNAP_ST_NONFINITE : SNAP_ST_MAX_ITER);
       break;
     }
-
-    // ------------------------------------------------ step p = -(d + J^T lam+)/W
-    // backward: the step is the adjoint; write it and stop
-    auto step_at = [&](int s, int j, int k, double uu) -> double {
-      const double d = uu - uhat_at(s, j);
-      const double a = (k < nr) ? coef_a(f2, c, uu) : 0.0;
-      double jt = d + a * ((k < nr) ? sh.lamp[k] : 0.0) + (k >= 1 ? sh.lamp[k - 1] : 0.0)
-                + (k == 0 ? lampic[j] : 0.0);
-      return -jt / sh.W[k];
-    };
     if (bwd) {
+      // the adjoint is the step of the linearized system: write it and stop
+      const int eb = opaque(base), gq = opaque(grp);
 #pragma unroll
-      for (int s = 0; s < SPW; ++s) {
-        const int k = slab_of(s);
-        if (k >= nt) continue;
+      for (int r = 0; r < RMAX; ++r) {
+        if (!live(r)) continue;
+        const int k = gq + NG * r;
+        const double lk = (k < nr) ? sh.lamp[k] : 0.0;
+        const double lkm = (k >= 1 && k < nt) ? sh.lamp[k - 1] : 0.0;
+        const double rW = k < nt ? sh.rW[k] : 1.0;
 #pragma unroll
         for (int j = 0; j < XPL; ++j) {
-          const int x = xof(j);
-          if (x < nx) A.grad_uhat[D.var_off + (int64_t)k * nx + x] = step_at(s, j, k, u[s][j]);
+          const int x = xat(j);
+          if (k < nt && x < nx) {
+            const double uu = u[r][j];
+            const double lic = (r == 0 && k == 0) ? sh.lampic[x] : 0.0;
+            const int e = eidx_from(eb, r, j);
+            const double jt = (uu - uhl[e]) + coef(k, uu) * lk + lkm + lic;
+            A.grad_uhat[vo + e] = -jt * rW;
+          }
         }
       }
       status = SNAP_ST_CONVERGED;
       break;
     }
-
-    // the step, once, into registers (the line search and the update reuse it)
-    double pst[SPW][XPL];
-#pragma unroll
-    for (int s = 0; s < SPW; ++s) {
-      const int k = slab_of(s);
-#pragma unroll
-      for (int j = 0; j < XPL; ++j)
-        pst[s][j] = (k < nt && xof(j) < nx) ? step_at(s, j, k, u[s][j]) : 0.0;
-    }
-
-    // merit phi = 1/2||u - u_hat||^2 + mu*||h||_1 and its directional derivative
-    double lmax = 0.0;
-    if (w == 0) {
-      double lm = 0.0;
-#pragma unroll
-      for (int j = 0; j < XPL; ++j) lm = fmax(lm, fabs(lampic[j]));
-      for (int k = lane; k < nr; k += kWave) lm = fmax(lm, fabs(sh.lamp[k]));
-      lm = wave_max(lm);
-      if (lane == 0) sh.scal[4] = lm;
-    }
-    {
-      double pp = 0.0, dd = 0.0;
-#pragma unroll
-      for (int s = 0; s < SPW; ++s) {
-        const int k = slab_of(s);
-        if (k >= nt) continue;
-#pragma unroll
-        for (int j = 0; j < XPL; ++j) {
-          if (xof(j) < nx) {
-            const double d = u[s][j] - uhat_at(s, j);
-            const double p = pst[s][j];
-            pp += p * p;
-            dd += d * p;
-          }
-        }
-      }
-      pp = wave_sum(pp); dd = wave_sum(dd);
-      if (lane == 0) { sh.red[w][1] = pp; sh.red[w][2] = dd; }
-    }
+    // ------------------------------------------------ step and trial point at alpha = 1
+    sums_pass(sh.lamp, sh.lampic, true);
     lds_barrier();
-    lmax = fmax(lmax, sh.scal[4]);
-    mu = fmax(mu, 1.1 * lmax + 1e-8);
-    // the merit change along p is formed from differences (alpha d.p +
-    // alpha^2/2 p.p + mu(||h_t||_1 - ||h||_1)), so rounding of the large sums
-    // in phi itself never decides acceptance
-    double pp = 0.0, dd = 0.0;
-    for (int q = 0; q < kSlabWaves; ++q) { pp += sh.red[q][1]; dd += sh.red[q][2]; }
-    const double h1_0 = sh.scal[3];
-    const double dphi = dd - mu * h1_0;
-    lds_barrier();
-
-    // ------------------------------------------------ backtracking line search
-    double alpha = 1.0;
-    int accepted = 0;
-    for (int ls = 0; ls <= A.opt.max_ls; ++ls) {
-#pragma unroll
-      for (int s = 0; s < SPW; ++s) {
-        const int k = slab_of(s);
-        if (k >= nt) continue;
-        double S1 = 0, S2 = 0;
-#pragma unroll
-        for (int j = 0; j < XPL; ++j) {
-          if (xof(j) < nx) {
-            const double ut = u[s][j] + alpha * pst[s][j];
-            S1 += ut; S2 += ut * (1.0 - ut);
-          }
-        }
-        S1 = wave_sum(S1); S2 = wave_sum(S2);
-        if (lane == 0) { sh.S1[k] = S1; sh.S2[k] = S2; }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (w == 0) {
-        double hic1 = 0.0;
-#pragma unroll
-        for (int j = 0; j < XPL; ++j) {
-          if (xof(j) < nx) {
-            const double ut = u[0][j] + alpha * pst[0][j];
-            hic1 += fabs(ut - gic[j]);
-          }
-        }
-        hic1 = wave_sum(hic1);
-        if (lane == 0) sh.scal[5] = hic1;
-      }
-      lds_barrier();
-      if (w == 0) {
-        double h1 = sh.scal[5];
-        for (int k = lane; k < nr; k += kWave) {
-          double hk = f2 ? sh.S1[k + 1] - sh.S1[k] - c * sh.S2[k] : sh.S1[k + 1] - m0;
-          h1 += fabs(hk);
-        }
-        h1 = wave_sum(h1);
-        const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (h1 - h1_0);
-        // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
-        // ||h||_1 along p sits below the rounding of the row sums
-        int ok = (dphi_t <= 1e-4 * alpha * dphi) || !(dphi < 0.0) || hinf <= 1e-6 ? 1 : 0;
-        if (lane == 0) sh.flag[1] = ok;
-      }
-      lds_barrier();
-      if (sh.flag[1]) { accepted = 1; break; }
-      alpha *= 0.5;
-      ++backtracks;
-    }
-    if (!accepted) {
-      status = SNAP_ST_LS_FAIL;
-      break;
-    }
-    // ------------------------------------------------ accept: u += alpha p, lam += alpha (lam+ - lam)
-#pragma unroll
-    for (int s = 0; s < SPW; ++s) {
-      const int k = slab_of(s);
-      if (k >= nt) continue;
-#pragma unroll
-      for (int j = 0; j < XPL; ++j)
-        if (xof(j) < nx) u[s][j] += alpha * pst[s][j];
-    }
-    // every thread computed its step with the old u above; now update lam, W
-    lds_barrier();
-    if (w == 0) {
-#pragma unroll
-      for (int j = 0; j < XPL; ++j) lamic[j] += alpha * (lampic[j] - lamic[j]);
-    }
-    for (int k = threadIdx.x; k < nr; k += kSlabThreads) {
-      double l = sh.lam[k] + alpha * (sh.lamp[k] - sh.lam[k]);
-      sh.lam[k] = l;
-      sh.W[k] = fmax(1.0 + 2.0 * c * l, wfloor);
-    }
-    ++iters;
-    lds_barrier();
+    pend = true;
   }
 
   // ---------------------------------------------------------------- outputs
   if (!bwd) {
+    const int eb = opaque(base), gq = opaque(grp);
 #pragma unroll
-    for (int s = 0; s < SPW; ++s) {
-      const int k = slab_of(s);
-      if (k >= nt) continue;
+    for (int r = 0; r < RMAX; ++r) {
+      const int k = gq + NG * r;
 #pragma unroll
       for (int j = 0; j < XPL; ++j) {
-        const int x = xof(j);
-        if (x < nx) A.u[D.var_off + (int64_t)k * nx + x] = u[s][j];
+        const int x = xat(j);
+        if (k < nt && x < nx) A.u[vo + eidx_from(eb, r, j)] = u[r][j];
       }
     }
-    if (w == 0) {
-#pragma unroll
-      for (int j = 0; j < XPL; ++j)
-        if (xof(j) < nx) A.lam[D.row_off + xof(j)] = lamic[j];
-    }
-    for (int k = threadIdx.x; k < nr; k += kSlabThreads) A.lam[D.row_off + nx + k] = sh.lam[k];
+    for (int x = tid; x < nx; x += NT) A.lam[D.row_off + x] = sh.lamic[x];
+    for (int k = tid; k < nr; k += NT) A.lam[D.row_off + nx + k] = sh.lam[k];
   }
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     snap_sample_stats st;
     st.status = status;
     st.newton_iters = iters;
@@ -543,47 +656,69 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_kernel(KernelArgs A) {
   }
 }
 
-// ------------------------------------------------------------------ dispatch
-using SlabLaunch = void (*)(const KernelArgs&, hipStream_t);
+// ------------------------------------------------------------------ classes
+// (waves, lanes per slab group, x per lane, rounds, u_hat LDS capacity)
+struct SlabCfg { int nw, g, xpl, rmax, uhn; };
+constexpr SlabCfg kCfg[] = {
+    {8, 16, 4, 1, 2048},     // 0: nx <= 64,  nt <= 32
+    {8, 8, 8, 2, 8192},      // 1: nx <= 64,  nt <= 128
+    {8, 16, 8, 4, 16384},    // 2: nx <= 128, nt <= 128
+};
+constexpr int kNumCfg = sizeof(kCfg) / sizeof(kCfg[0]);
+constexpr int kWideBase = 100;   // classes >= 100: the wide-grid kernel
 
-template <int SPW, int XPL, typename TS>
-static void launch_slab(const KernelArgs& a, hipStream_t st) {
-  constexpr bool ureg = SPW * XPL <= 26;
-  hipLaunchKernelGGL((slab_kernel<SPW, XPL, ureg, TS>), dim3(a.count), dim3(kSlabThreads), 0, st, a);
+bool cfg_fits(const SlabCfg& f, int nx, int nt) {
+  return nx >= 1 && nt >= 1 && nx <= f.g * f.xpl && nt <= kMaxNt &&
+         nt <= (f.nw * kWave / f.g) * f.rmax && nx * nt <= f.uhn;
+}
+
+template <int I, typename TS>
+void launch_cfg(const KernelArgs& a, hipStream_t st) {
+  constexpr SlabCfg f = kCfg[I];
+  hipLaunchKernelGGL((slab_kernel<f.nw, f.g, f.xpl, f.rmax, f.uhn, TS>), dim3(a.count),
+                     dim3(f.nw * kWave), 0, st, a);
 }
 
 template <typename TS>
-static SlabLaunch pick_slab(int spw, int xpl) {
-#define SNAP_SLAB_CASE(S, X) if (spw <= S && xpl == X) return &launch_slab<S, X, TS>;
-#define SNAP_SLAB_ROW(X) SNAP_SLAB_CASE(1, X) SNAP_SLAB_CASE(2, X) SNAP_SLAB_CASE(4, X) \
-                         SNAP_SLAB_CASE(8, X) SNAP_SLAB_CASE(13, X) SNAP_SLAB_CASE(16, X)
-  SNAP_SLAB_ROW(1) SNAP_SLAB_ROW(2) SNAP_SLAB_ROW(3) SNAP_SLAB_ROW(4)
-#undef SNAP_SLAB_ROW
-#undef SNAP_SLAB_CASE
-  return nullptr;
+int launch_index(const KernelArgs& a, int i, hipStream_t st) {
+  switch (i) {
+    case 0: launch_cfg<0, TS>(a, st); break;
+    case 1: launch_cfg<1, TS>(a, st); break;
+    case 2: launch_cfg<2, TS>(a, st); break;
+    default: return SNAP_EUNSUPPORTED;
+  }
+  return 0;
 }
 
-// Kernel class of a (nx, nt) shape: index of the (SPW, XPL) instantiation, or -1.
+// class override for launch-shape sweeps: SNAP_SLAB_CLASS=<index>
+int forced_class() {
+  static const int v = [] {
+    const char* e = getenv("SNAP_SLAB_CLASS");
+    return e ? atoi(e) : -1;
+  }();
+  return v;
+}
+
+}  // namespace
+
+// Kernel class of an (nx, nt) shape: the first class whose grid capacity and
+// u_hat staging cover it; wider grids go to the wide-grid kernel.
 int slab_class(int nx, int nt) {
-  if (nt < 1 || nt > kMaxNt || nx < 1 || nx > 4 * kWave) return -1;
-  const int spw = (nt + kSlabWaves - 1) / kSlabWaves;
-  const int xpl = (nx + kWave - 1) / kWave;
-  static const int spws[] = {1, 2, 4, 8, 13, 16};
-  for (int i = 0; i < 6; ++i)
-    if (spw <= spws[i]) return i * 4 + (xpl - 1);
-  return -1;
+  const int f = forced_class();
+  if (f >= 0 && f < kNumCfg && cfg_fits(kCfg[f], nx, nt)) return f;
+  for (int i = 0; i < kNumCfg; ++i)
+    if (cfg_fits(kCfg[i], nx, nt)) return i;
+  const int wc = slab_wide_class(nx, nt);
+  return wc < 0 ? -1 : kWideBase + wc;
 }
 
 // Host entry used by the plan: one workgroup per listed sample; every sample
 // of the launch belongs to kernel class `cls` (shapes may differ).
 int slab_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st) {
   if (a.count == 0) return 0;
-  static const int spws[] = {1, 2, 4, 8, 13, 16};
-  if (cls < 0 || cls >= 24) return SNAP_EUNSUPPORTED;
-  const int spw = spws[cls / 4], xpl = cls % 4 + 1;
-  SlabLaunch f = mixed ? pick_slab<float>(spw, xpl) : pick_slab<double>(spw, xpl);
-  if (!f) return SNAP_EUNSUPPORTED;
-  f(a, st);
+  if (cls >= kWideBase) return slab_wide_launch(a, cls - kWideBase, mixed, st);
+  const int rc = mixed ? launch_index<float>(a, cls, st) : launch_index<double>(a, cls, st);
+  if (rc) return rc;
   return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP;
 }
 
