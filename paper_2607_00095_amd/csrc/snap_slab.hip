@@ -52,72 +52,83 @@ constexpr double kWFloor = 0.1;
 
 template <typename TS>
 struct PcrBuf {
-  TS a[2][kMaxNt], b[2][kMaxNt], c[2][kMaxNt], d[2][kMaxNt], rb[2][kMaxNt];
+  TS a[2][kWave], c[2][kWave], d[2][kWave], rb[2][kWave];
+  TS oa[kWave], oc[kWave], od[kWave], orb[kWave];   // odd equations
+  double xe[kWave + 1];                               // even unknowns
 };
 
-// Parallel cyclic reduction of the symmetric tridiagonal system with
-// diagonal Td[0..n), off-diagonal To[k] = T_{k,k+1} and right-hand side rhs,
-// by ONE wavefront (n <= 128, two equations per lane), in precision TS; one
-// reciprocal per equation and level.  The result is written to x (LDS).
+// Solve the symmetric tridiagonal system with diagonal Td[0..n),
+// off-diagonal To[k] = T_{k,k+1} and right-hand side rhs by ONE wavefront
+// (n <= 128), in precision TS; the result goes to x (LDS).  Lane l holds
+// equations 2l and 2l+1.  One level of cyclic reduction eliminates the odd
+// unknowns (each even equation takes its two odd neighbours), parallel cyclic
+// reduction solves the <= 64 even equations, one per lane, and the odd
+// unknowns follow by back-substitution.  One reciprocal per equation and level.
 template <typename TS>
 __device__ void pcr_solve(int n, const double* Td, const double* To, const double* rhs,
                           double* x, PcrBuf<TS>& B) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int j = lane + kWave * e;
-    if (j < n) {
-      const TS bj = (TS)Td[j];
-      B.a[0][j] = j > 0 ? (TS)To[j - 1] : (TS)0;
-      B.b[0][j] = bj;
-      B.c[0][j] = j < n - 1 ? (TS)To[j] : (TS)0;
-      B.d[0][j] = (TS)rhs[j];
-      B.rb[0][j] = rcp_nr(bj);
-    }
-  }
+  const int l = threadIdx.x & (kWave - 1);
+  const int j0 = 2 * l, j1 = 2 * l + 1;
+  const int m = (n + 1) / 2;   // even equations
+  const bool v0 = j0 < n, v1 = j1 < n;
+  const TS a0 = (v0 && j0 > 0) ? (TS)To[j0 - 1] : (TS)0;
+  const TS b0 = v0 ? (TS)Td[j0] : (TS)1;
+  const TS c0 = (v0 && j0 + 1 < n) ? (TS)To[j0] : (TS)0;
+  const TS d0 = v0 ? (TS)rhs[j0] : (TS)0;
+  const TS a1 = v1 ? (TS)To[j1 - 1] : (TS)0;
+  const TS b1 = v1 ? (TS)Td[j1] : (TS)1;
+  const TS c1 = (v1 && j1 + 1 < n) ? (TS)To[j1] : (TS)0;
+  const TS d1 = v1 ? (TS)rhs[j1] : (TS)0;
+  const TS r1 = rcp_nr(b1);
+  B.oa[l] = a1; B.oc[l] = c1; B.od[l] = d1; B.orb[l] = r1;
   wave_sync();
+  // even equation 2l with odd neighbours 2l-1 (lane l-1) and 2l+1 (own)
+  TS A = 0, Bv = b0, C = 0, Dv = d0;
+  if (l > 0) {
+    const TS al = -a0 * B.orb[l - 1];
+    A = al * B.oa[l - 1];
+    Bv += al * B.oc[l - 1];
+    Dv += al * B.od[l - 1];
+  }
+  {
+    const TS ga = -c0 * r1;
+    C = ga * c1;
+    Bv += ga * a1;
+    Dv += ga * d1;
+  }
+  if (l >= m) { A = 0; Bv = 1; C = 0; Dv = 0; }
+  TS rB = rcp_nr(Bv);
   int cur = 0;
-  for (int s = 1; s < n; s <<= 1) {
-    TS na[2], nb[2], nc[2], nd[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int j = lane + kWave * e;
-      TS an = 0, bj = 1, cn = 0, dj = 0;
-      if (j < n) {
-        const TS aj = B.a[cur][j], cj = B.c[cur][j];
-        bj = B.b[cur][j];
-        dj = B.d[cur][j];
-        if (j - s >= 0) {
-          const TS al = -aj * B.rb[cur][j - s];
-          an = al * B.a[cur][j - s];
-          bj += al * B.c[cur][j - s];
-          dj += al * B.d[cur][j - s];
-        }
-        if (j + s < n) {
-          const TS ga = -cj * B.rb[cur][j + s];
-          cn = ga * B.c[cur][j + s];
-          bj += ga * B.a[cur][j + s];
-          dj += ga * B.d[cur][j + s];
-        }
-      }
-      na[e] = an; nb[e] = bj; nc[e] = cn; nd[e] = dj;
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int j = lane + kWave * e;
-      if (j < n) {
-        B.a[cur ^ 1][j] = na[e]; B.b[cur ^ 1][j] = nb[e];
-        B.c[cur ^ 1][j] = nc[e]; B.d[cur ^ 1][j] = nd[e];
-        B.rb[cur ^ 1][j] = rcp_nr(nb[e]);
-      }
-    }
+  for (int s = 1; s < m; s <<= 1) {
+    B.a[cur][l] = A; B.c[cur][l] = C; B.d[cur][l] = Dv; B.rb[cur][l] = rB;
     wave_sync();
+    if (l < m) {
+      TS An = 0, Cn = 0;
+      if (l - s >= 0) {
+        const TS al = -A * B.rb[cur][l - s];
+        An = al * B.a[cur][l - s];
+        Bv += al * B.c[cur][l - s];
+        Dv += al * B.d[cur][l - s];
+      }
+      if (l + s < m) {
+        const TS ga = -C * B.rb[cur][l + s];
+        Cn = ga * B.c[cur][l + s];
+        Bv += ga * B.a[cur][l + s];
+        Dv += ga * B.d[cur][l + s];
+      }
+      A = An; C = Cn;
+      rB = rcp_nr(Bv);
+    }
     cur ^= 1;
   }
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int j = lane + kWave * e;
-    if (j < n) x[j] = (double)(B.d[cur][j] * B.rb[cur][j]);
+  const double xe = (double)(Dv * rB);
+  B.xe[l] = xe;
+  if (l == kWave - 1) B.xe[kWave] = 0.0;
+  wave_sync();
+  if (v0) x[j0] = xe;
+  if (v1) {
+    const TS xn = (j1 + 1 < n) ? (TS)B.xe[l + 1] : (TS)0;
+    x[j1] = (double)((d1 - a1 * (TS)xe - c1 * xn) * r1);
   }
   wave_sync();
 }
