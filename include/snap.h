@@ -69,9 +69,20 @@ enum snap_precision {
 };
 
 enum snap_flags {
-  SNAP_FLAG_KEEP_FACTOR = 1  /* leave a factor of the KKT system taken at the
+  SNAP_FLAG_KEEP_FACTOR = 1, /* leave a factor of the KKT system taken at the
                                 returned point in the workspace, for
                                 snap_project_backward */
+  SNAP_FLAG_GRAPH = 2        /* run each call's whole launch sequence (for the
+                                banded family: every Newton iteration's factor,
+                                solve, step and evaluation launches) from a HIP
+                                graph.  The graph is captured on the first call
+                                and replayed while the array and workspace
+                                pointers stay the same (they are re-captured
+                                when they change); the plan keeps one graph per
+                                direction.  Needs a non-null stream: on the
+                                null stream the call runs its launches
+                                directly.  Calls with this flag on one plan
+                                from several host threads are serialized. */
 };
 
 /* call-level return codes */

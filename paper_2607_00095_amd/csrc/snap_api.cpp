@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -39,6 +40,12 @@ struct Group {
 
 constexpr int kStreams = 4;   // groups are spread over this many internal streams
 
+// A captured launch sequence and the call arguments it was captured with.
+struct GraphSlot {
+  hipGraphExec_t exec = nullptr;
+  KernelArgs key{};
+};
+
 }  // namespace
 
 struct snap_plan_s {
@@ -54,6 +61,8 @@ struct snap_plan_s {
   int device = 0;
   std::vector<hipStream_t> streams;     // fork/join of independent groups
   std::vector<hipEvent_t> events;       // [0] fork, [1..] join per stream
+  GraphSlot graphs[2];                  // SNAP_FLAG_GRAPH: forward, backward
+  std::mutex graph_mu;
 };
 
 namespace {
@@ -77,6 +86,8 @@ int64_t aux_of(const snap_sample_desc& d) {
 
 void free_plan(snap_plan p) {
   if (!p) return;
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   for (auto& e : p->events) (void)hipEventDestroy(e);
   for (auto& s : p->streams) (void)hipStreamDestroy(s);
   for (auto& g : p->groups)
@@ -248,6 +259,48 @@ static int run(snap_plan plan, KernelArgs a, hipStream_t st) {
   return SNAP_SUCCESS;
 }
 
+// the pointers a captured graph has baked into its kernel arguments
+static bool same_call(const KernelArgs& x, const KernelArgs& y) {
+  return x.uhat == y.uhat && x.aux == y.aux && x.u == y.u && x.lam == y.lam &&
+         x.stats == y.stats && x.grad_u == y.grad_u && x.grad_uhat == y.grad_uhat &&
+         x.ws == y.ws && x.backward == y.backward;
+}
+
+// SNAP_FLAG_GRAPH: replay the call's launches from a graph captured on the
+// first call with these arguments (the fork/join over the plan's streams is
+// captured through its events).
+static int run_graph(snap_plan plan, const KernelArgs& a, hipStream_t st) {
+  if (st == nullptr) return run(plan, a, st);   // the null stream cannot be captured
+  std::lock_guard<std::mutex> lock(plan->graph_mu);
+  GraphSlot& g = plan->graphs[a.backward ? 1 : 0];
+  if (!g.exec || !same_call(g.key, a)) {
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    }
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return SNAP_EHIP;
+    const int rc = run(plan, a, st);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rc != 0 || ec != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc != 0 ? rc : SNAP_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g.exec = nullptr;
+      return SNAP_EHIP;
+    }
+    g.key = a;
+  }
+  return hipGraphLaunch(g.exec, st) == hipSuccess ? SNAP_SUCCESS : SNAP_EHIP;
+}
+
+static int dispatch(snap_plan plan, const KernelArgs& a, hipStream_t st) {
+  return (plan->opt.flags & SNAP_FLAG_GRAPH) ? run_graph(plan, a, st) : run(plan, a, st);
+}
+
 int snap_project(snap_plan plan, const double* uhat, const double* aux, double* u_out,
                  double* lambda_out, snap_sample_stats* stats, void* workspace, void* stream) {
   if (!plan) return SNAP_EINVAL;
@@ -267,7 +320,7 @@ int snap_project(snap_plan plan, const double* uhat, const double* aux, double* 
   a.ws_off = plan->d_ws_off;
   a.opt = plan->opt;
   a.backward = 0;
-  return run(plan, a, (hipStream_t)stream);
+  return dispatch(plan, a, (hipStream_t)stream);
 }
 
 int snap_project_backward(snap_plan plan, const double* u, const double* lambda, const double* aux,
@@ -294,7 +347,7 @@ int snap_project_backward(snap_plan plan, const double* u, const double* lambda,
     // the slab kernels read aux (IC targets) unconditionally
     return SNAP_EINVAL;
   }
-  return run(plan, a, (hipStream_t)stream);
+  return dispatch(plan, a, (hipStream_t)stream);
 }
 
 int snap_plan_destroy(snap_plan plan) {
