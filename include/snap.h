@@ -72,7 +72,7 @@ enum snap_flags {
   SNAP_FLAG_KEEP_FACTOR = 1, /* leave a factor of the KKT system taken at the
                                 returned point in the workspace, for
                                 snap_project_backward */
-  SNAP_FLAG_GRAPH = 2        /* run each call's whole launch sequence (for the
+  SNAP_FLAG_GRAPH = 2,       /* run each call's whole launch sequence (for the
                                 banded family: every Newton iteration's factor,
                                 solve, step and evaluation launches) from a HIP
                                 graph.  The graph is captured on the first call
@@ -83,6 +83,19 @@ enum snap_flags {
                                 null stream the call runs its launches
                                 directly.  Calls with this flag on one plan
                                 from several host threads are serialized. */
+  SNAP_FLAG_AUTOTUNE = 4     /* snap_plan_create times every launch shape that
+                                can run a group of samples (lanes per time slab
+                                and rounds for the slab-row families; wavefronts
+                                sharing one sample's band window for the banded
+                                family) on a synthetic copy of the group (same
+                                shapes and sample count, two Newton iterations)
+                                and keeps the fastest.  Plan creation then
+                                synchronizes the device and allocates temporary
+                                device memory of the size of the call's arrays and
+                                workspace.  Choices are cached per process.  A
+                                shape changes the summation order of some
+                                reductions, so results may differ from the
+                                untuned plan's in the last bits. */
 };
 
 /* call-level return codes */
@@ -181,6 +194,23 @@ int snap_project(snap_plan plan, const double* uhat, const double* aux, double* 
 int snap_project_backward(snap_plan plan, const double* u, const double* lambda,
                           const double* aux, void* workspace, const double* grad_u,
                           double* grad_uhat, snap_sample_stats* stats, void* stream);
+
+/* Text description of the plan's launch groups, one line per group
+ * ("group <i>: <slab|band> class <c>, <w> wavefronts per workgroup, <n> samples").
+ * Writes at most len bytes into buf (NUL-terminated when len > 0); *needed, if
+ * not NULL, receives the full length without the NUL. */
+int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed);
+
+/* Kernel classes (launch shapes) that can run launch group `group` of the plan,
+ * the one in use first; *count receives how many there are (at most cap are
+ * written).  Groups are numbered as in snap_plan_describe. */
+int snap_plan_group_classes(snap_plan plan, int32_t group, int32_t* classes, int32_t cap,
+                            int32_t* count);
+
+/* Run launch group `group` with kernel class `cls`, one of those listed by
+ * snap_plan_group_classes (for instance a choice saved from an autotuned
+ * plan).  Drops any captured graph.  Must not race with calls on the plan. */
+int snap_plan_set_group_class(snap_plan plan, int32_t group, int32_t cls);
 
 int snap_plan_destroy(snap_plan plan);
 

@@ -11,7 +11,7 @@ import torch
 
 MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY = 1, 2, 3, 4
 PREC_FP64, PREC_MIXED = 0, 1
-FLAG_KEEP_FACTOR, FLAG_GRAPH = 1, 2
+FLAG_KEEP_FACTOR, FLAG_GRAPH, FLAG_AUTOTUNE = 1, 2, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -67,12 +67,16 @@ def _load():
     lib.snap_project.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.snap_project_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.snap_plan_destroy.argtypes = [vp]
+    lib.snap_plan_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.snap_plan_group_classes.argtypes = [vp, i32, C.POINTER(i32), i32, C.POINTER(i32)]
+    lib.snap_plan_set_group_class.argtypes = [vp, i32, i32]
     lib.snap_error_string.argtypes = [C.c_int]
     lib.snap_error_string.restype = C.c_char_p
     lib.snap_status_string.argtypes = [C.c_int]
     lib.snap_status_string.restype = C.c_char_p
     for f in ("snap_plan_create", "snap_plan_workspace_bytes", "snap_plan_sizes", "snap_project",
-              "snap_project_backward", "snap_plan_destroy"):
+              "snap_project_backward", "snap_plan_destroy", "snap_plan_describe",
+              "snap_plan_group_classes", "snap_plan_set_group_class"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -132,6 +136,26 @@ class Plan:
     @classmethod
     def from_batch(cls, batch, options: Optional[Options] = None, device=None):
         return cls(batch.samples, batch.var_off, batch.row_off, batch.aux_off, options, device)
+
+    def describe(self) -> str:
+        """One line per launch group: family kind, kernel class, wavefronts, samples."""
+        lib = _load()
+        need = C.c_size_t()
+        _check(lib.snap_plan_describe(self._h, None, 0, C.byref(need)), "snap_plan_describe")
+        buf = C.create_string_buffer(need.value + 1)
+        _check(lib.snap_plan_describe(self._h, buf, need.value + 1, None), "snap_plan_describe")
+        return buf.value.decode()
+
+    def group_classes(self, group: int):
+        """Kernel classes that can run launch group `group`, the one in use first."""
+        lib = _load()
+        arr = (C.c_int32 * 16)()
+        n = C.c_int32()
+        _check(lib.snap_plan_group_classes(self._h, group, arr, 16, C.byref(n)), "snap_plan_group_classes")
+        return [arr[i] for i in range(min(n.value, 16))]
+
+    def set_group_class(self, group: int, cls: int):
+        _check(_load().snap_plan_set_group_class(self._h, group, cls), "snap_plan_set_group_class")
 
     def new_workspace(self) -> torch.Tensor:
         # 256-byte aligned: torch's caching allocator returns 512-byte aligned blocks

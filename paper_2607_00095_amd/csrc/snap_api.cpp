@@ -5,8 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
+#include <string>
 #include <mutex>
 #include <new>
 #include <tuple>
@@ -21,6 +24,10 @@ int slab_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st);
 int band_class(int nx, int nt);
 int band_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st);
 size_t band_workspace_bytes(int nx, int nt, bool mixed);
+int slab_variants(int nx, int nt, int* out, int cap);
+int band_variants(int cls, int* out, int cap);
+int slab_waves(int cls);
+int band_waves(int cls);
 }  // namespace snap
 
 using namespace snap;
@@ -101,6 +108,164 @@ bool options_valid(const snap_options& o) {
   return o.tol_h > 0 && o.tol_s > 0 && o.max_newton >= 1 && o.max_ls >= 0 &&
          (o.precision == SNAP_PREC_FP64 || o.precision == SNAP_PREC_MIXED);
 }
+
+// ---------------------------------------------------------------- autotuner
+// SNAP_FLAG_AUTOTUNE: for every group with more than one buildable launch
+// shape, time each on a synthetic copy of the group (same shapes, same sample
+// count, seeded smooth fields plus noise, two Newton iterations) and keep the
+// fastest.  Choices are cached per process by group signature.
+
+// candidate classes common to every sample of a group
+std::vector<int> group_candidates(const snap_plan_s& p, const Group& g) {
+  std::vector<int> cand;
+  for (size_t i = 0; i < g.ids.size(); ++i) {
+    const snap_sample_desc& d = p.descs[g.ids[i]];
+    int v[8];
+    const int n = g.kind == 0 ? slab_variants(d.nx, d.nt, v, 8) : band_variants(g.cls, v, 8);
+    std::vector<int> mine(v, v + n);
+    if (i == 0) {
+      cand = mine;
+    } else {
+      std::vector<int> keep;
+      for (int c : cand)
+        if (std::find(mine.begin(), mine.end(), c) != mine.end()) keep.push_back(c);
+      cand = keep;
+    }
+  }
+  return cand;
+}
+
+std::string group_signature(const snap_plan_s& p, const Group& g) {
+  std::string k = std::to_string(g.kind) + ":" + std::to_string(g.cls) + ":" +
+                  std::to_string(p.opt.precision) + ":" + std::to_string(g.ids.size());
+  for (int32_t id : g.ids) {
+    const snap_sample_desc& d = p.descs[id];
+    k += ":" + std::to_string(d.family) + "," + std::to_string(d.nx) + "," + std::to_string(d.nt);
+  }
+  return k;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+// deterministic pseudo-random numbers in [-0.5, 0.5) (64-bit LCG)
+struct Lcg {
+  uint64_t s;
+  double next() {
+    s = s * 6364136223846793005ull + 1442695040888963407ull;
+    return (double)(s >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+};
+
+int64_t rows_of(const snap_sample_desc& d);
+int64_t aux_of(const snap_sample_desc& d);
+int launch_group_cls(const snap_plan_s& p, KernelArgs a, const Group& g, int cls, hipStream_t st);
+
+// Time the candidates; returns the fastest class (or the group's own class
+// if anything fails: tuning never changes results, only launch shapes).
+int tune_group(const snap_plan_s& p, const Group& g, const std::vector<int>& cand,
+               size_t (*ws_need)(const snap_sample_desc&, bool)) {
+  const bool mixed = p.opt.precision == SNAP_PREC_MIXED;
+  const int n = (int)g.ids.size();
+  std::vector<snap_sample_desc> d(n);
+  std::vector<int64_t> off(n);
+  std::vector<int32_t> order(n);
+  int64_t nv = 0, nr = 0, na = 0;
+  size_t ws = 0;
+  for (int i = 0; i < n; ++i) {
+    d[i] = p.descs[g.ids[i]];
+    d[i].var_off = nv; d[i].row_off = nr; d[i].aux_off = na;
+    nv += (int64_t)d[i].nx * d[i].nt; nr += rows_of(d[i]); na += aux_of(d[i]);
+    off[i] = (int64_t)ws;
+    ws += (ws_need(d[i], mixed) + 255) & ~(size_t)255;
+    order[i] = i;
+  }
+  // seeded fields: smooth profile plus noise, aux from the t = 0 slab
+  std::vector<double> uh((size_t)nv), aux((size_t)std::max<int64_t>(na, 1), 0.0);
+  Lcg rng{0x5eed5eedull};
+  for (int i = 0; i < n; ++i) {
+    const snap_sample_desc& q = d[i];
+    const bool burgers = q.family == SNAP_BURGERS_LF;
+    for (int k = 0; k < q.nt; ++k)
+      for (int x = 0; x < q.nx; ++x) {
+        const double t = 6.283185307179586 * x / q.nx;
+        const double base = burgers ? 0.5 * std::sin(t) : 0.5 + 0.3 * std::sin(t);
+        uh[q.var_off + (int64_t)k * q.nx + x] = base + 0.02 * rng.next();
+      }
+    if (q.family == SNAP_MASS_IC || q.family == SNAP_FISHER_KPP) {
+      double m0 = 0.0;
+      for (int x = 0; x < q.nx; ++x) {
+        const double t = 6.283185307179586 * x / q.nx;
+        aux[q.aux_off + x] = 0.5 + 0.3 * std::sin(t);
+        m0 += aux[q.aux_off + x];
+      }
+      if (q.family == SNAP_MASS_IC) aux[q.aux_off + q.nx] = m0;
+    }
+  }
+  void *dd = nullptr, *dord = nullptr, *doff = nullptr, *duh = nullptr, *daux = nullptr,
+       *du = nullptr, *dlam = nullptr, *dst = nullptr, *dws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t st = nullptr;
+  int best = g.cls;
+  bool ok = hipMalloc(&dd, sizeof(snap_sample_desc) * n) == hipSuccess &&
+            hipMalloc(&dord, sizeof(int32_t) * n) == hipSuccess &&
+            hipMalloc(&doff, sizeof(int64_t) * n) == hipSuccess &&
+            hipMalloc(&duh, sizeof(double) * nv) == hipSuccess &&
+            hipMalloc(&daux, sizeof(double) * aux.size()) == hipSuccess &&
+            hipMalloc(&du, sizeof(double) * nv) == hipSuccess &&
+            hipMalloc(&dlam, sizeof(double) * std::max<int64_t>(nr, 1)) == hipSuccess &&
+            hipMalloc(&dst, sizeof(snap_sample_stats) * n) == hipSuccess &&
+            hipMalloc(&dws, std::max<size_t>(ws, 256)) == hipSuccess &&
+            hipMemcpy(dd, d.data(), sizeof(snap_sample_desc) * n, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(dord, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(doff, off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(duh, uh.data(), sizeof(double) * nv, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(daux, aux.data(), sizeof(double) * aux.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  if (ok) {
+    KernelArgs a{};
+    a.descs = (const snap_sample_desc*)dd;
+    a.uhat = (const double*)duh;
+    a.aux = (const double*)daux;
+    a.u = (double*)du;
+    a.lam = (double*)dlam;
+    a.stats = (snap_sample_stats*)dst;
+    a.ws = (unsigned char*)dws;
+    a.ws_off = (const int64_t*)doff;
+    a.opt = p.opt;
+    a.opt.max_newton = 2;
+    a.opt.flags = 0;
+    a.backward = 0;
+    Group tg = g;
+    tg.d_ids = (int32_t*)dord;
+    float best_ms = 0.0f;
+    for (int c : cand) {
+      float ms_min = -1.0f;
+      for (int rep = 0; rep < 3 && ok; ++rep) {   // first run warms up
+        ok = hipEventRecord(e0, st) == hipSuccess && launch_group_cls(p, a, tg, c, st) == 0 &&
+             hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        if (ok && rep > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+          ms_min = ms_min < 0.0f ? ms : std::min(ms_min, ms);
+      }
+      if (!ok) break;
+      if (ms_min >= 0.0f && (best_ms == 0.0f || ms_min < best_ms)) { best_ms = ms_min; best = c; }
+    }
+  }
+  if (!ok) best = g.cls;
+  if (st) (void)hipStreamSynchronize(st);
+  for (void* q : {dd, dord, doff, duh, daux, du, dlam, dst, dws})
+    if (q) (void)hipFree(q);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  (void)hipGetLastError();
+  return best;
+}
+
+size_t slab_ws_need(const snap_sample_desc&, bool) { return 0; }
+size_t band_ws_need(const snap_sample_desc& d, bool mixed) { return band_workspace_bytes(d.nx, d.nt, mixed); }
 
 }  // namespace
 
@@ -214,6 +379,21 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
       }
     }
   }
+  if (o.flags & SNAP_FLAG_AUTOTUNE) {
+    for (auto& g : p->groups) {
+      const std::vector<int> cand = group_candidates(*p, g);
+      if (cand.size() < 2) continue;
+      const std::string key = group_signature(*p, g);
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        g.cls = it->second;
+      } else {
+        g.cls = tune_group(*p, g, cand, g.kind == 0 ? &slab_ws_need : &band_ws_need);
+        g_tune_cache[key] = g.cls;
+      }
+    }
+  }
   *out = p;
   return SNAP_SUCCESS;
 }
@@ -232,11 +412,17 @@ int snap_plan_sizes(snap_plan plan, int64_t* total_vars, int64_t* total_rows, in
   return SNAP_SUCCESS;
 }
 
-static int launch_group(const snap_plan plan, KernelArgs a, const Group& g, hipStream_t st) {
-  const bool mixed = plan->opt.precision == SNAP_PREC_MIXED;
+namespace {
+int launch_group_cls(const snap_plan_s& p, KernelArgs a, const Group& g, int cls, hipStream_t st) {
+  const bool mixed = p.opt.precision == SNAP_PREC_MIXED;
   a.order = g.d_ids;
   a.count = (int32_t)g.ids.size();
-  return g.kind == 0 ? slab_launch(a, g.cls, mixed, st) : band_launch(a, g.cls, mixed, st);
+  return g.kind == 0 ? slab_launch(a, cls, mixed, st) : band_launch(a, cls, mixed, st);
+}
+}  // namespace
+
+static int launch_group(const snap_plan plan, KernelArgs a, const Group& g, hipStream_t st) {
+  return launch_group_cls(*plan, a, g, g.cls, st);
 }
 
 // One group: launch on the caller's stream.  Several: fork onto the plan's
@@ -348,6 +534,55 @@ int snap_project_backward(snap_plan plan, const double* u, const double* lambda,
     return SNAP_EINVAL;
   }
   return dispatch(plan, a, (hipStream_t)stream);
+}
+
+int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed) {
+  if (!plan || (len > 0 && !buf)) return SNAP_EINVAL;
+  std::string t;
+  for (size_t i = 0; i < plan->groups.size(); ++i) {
+    const Group& g = plan->groups[i];
+    char line[160];
+    std::snprintf(line, sizeof(line), "group %zu: %s class %d, %d wavefronts per workgroup, %zu samples\n",
+                  i, g.kind == 0 ? "slab" : "band", g.cls,
+                  g.kind == 0 ? slab_waves(g.cls) : band_waves(g.cls), g.ids.size());
+    t += line;
+  }
+  if (needed) *needed = t.size();
+  if (len > 0) {
+    const size_t c = std::min(len - 1, t.size());
+    std::memcpy(buf, t.data(), c);
+    buf[c] = 0;
+  }
+  return SNAP_SUCCESS;
+}
+
+int snap_plan_group_classes(snap_plan plan, int32_t group, int32_t* classes, int32_t cap,
+                            int32_t* count) {
+  if (!plan || group < 0 || group >= (int32_t)plan->groups.size() || cap < 0 || (cap > 0 && !classes))
+    return SNAP_EINVAL;
+  const Group& g = plan->groups[group];
+  std::vector<int> c = group_candidates(*plan, g);
+  auto it = std::find(c.begin(), c.end(), g.cls);
+  if (it != c.end()) std::rotate(c.begin(), it, it + 1);
+  if (count) *count = (int32_t)c.size();
+  for (int32_t i = 0; i < cap && i < (int32_t)c.size(); ++i) classes[i] = c[i];
+  return SNAP_SUCCESS;
+}
+
+int snap_plan_set_group_class(snap_plan plan, int32_t group, int32_t cls) {
+  if (!plan || group < 0 || group >= (int32_t)plan->groups.size()) return SNAP_EINVAL;
+  int32_t c[16], n = 0;
+  const int rc = snap_plan_group_classes(plan, group, c, 16, &n);
+  if (rc != SNAP_SUCCESS) return rc;
+  if (std::find(c, c + std::min<int32_t>(n, 16), cls) == c + std::min<int32_t>(n, 16)) return SNAP_EINVAL;
+  std::lock_guard<std::mutex> lock(plan->graph_mu);
+  plan->groups[group].cls = cls;
+  for (auto& gr : plan->graphs)
+    if (gr.exec) {
+      (void)hipGraphExecDestroy(gr.exec);
+      gr.exec = nullptr;
+    }
+  return SNAP_SUCCESS;
 }
 
 int snap_plan_destroy(snap_plan plan) {

@@ -1040,9 +1040,12 @@ static int pick_bb(int need) {
   return -1;
 }
 
-template <int BB, typename R>
+// Launch shape: NW wavefronts share one sample's block window.  Four let two
+// samples run per CU; eight halve each wavefront's share of the trailing
+// update.  Which wins depends on the batch, so both are built for BB <= 9 and
+// the plan's autotuner picks (wider bands always take eight).
+template <int BB, int NW, typename R>
 static void launch_band(const KernelArgs& a, hipStream_t st) {
-  constexpr int NW = BB <= 9 ? 4 : 8;
   const dim3 grid(a.count), block(NW * kWave);
   if (a.backward) {
     hipLaunchKernelGGL((band_adjoint<BB, NW, R>), grid, block, 0, st, a);
@@ -1062,22 +1065,44 @@ static void launch_band(const KernelArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((band_finish<BB, NW, R>), grid, block, 0, st, a);
 }
 
+// class = BB + kBandAlt * alt: alt 0 is the default launch shape (four
+// wavefronts for BB <= 9, eight above), alt 1 the alternative (eight, BB <= 9)
+constexpr int kBandAlt = 32;
+
 template <typename R>
-static int launch_bb(int bb, const KernelArgs& a, hipStream_t st) {
+static int launch_bb(int cls, const KernelArgs& a, hipStream_t st) {
+  const int bb = cls % kBandAlt, alt = cls / kBandAlt;
 #ifdef SNAP_BAND_QUICK
-  if (bb <= SNAP_BAND_QUICK) { launch_band<SNAP_BAND_QUICK, R>(a, st); return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP; }
+  if (bb <= SNAP_BAND_QUICK && alt == 0) {
+    launch_band<SNAP_BAND_QUICK, (SNAP_BAND_QUICK <= 9 ? 4 : 8), R>(a, st);
+    return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP;
+  }
   return SNAP_EUNSUPPORTED;
 #else
-  switch (bb) {
-    case 1: launch_band<1, R>(a, st); break;
-    case 2: launch_band<2, R>(a, st); break;
-    case 3: launch_band<3, R>(a, st); break;
-    case 5: launch_band<5, R>(a, st); break;
-    case 7: launch_band<7, R>(a, st); break;
-    case 9: launch_band<9, R>(a, st); break;
-    case 13: launch_band<13, R>(a, st); break;
-    case 17: launch_band<17, R>(a, st); break;
-    default: return SNAP_EUNSUPPORTED;
+  if (alt == 0) {
+    switch (bb) {
+      case 1: launch_band<1, 4, R>(a, st); break;
+      case 2: launch_band<2, 4, R>(a, st); break;
+      case 3: launch_band<3, 4, R>(a, st); break;
+      case 5: launch_band<5, 4, R>(a, st); break;
+      case 7: launch_band<7, 4, R>(a, st); break;
+      case 9: launch_band<9, 4, R>(a, st); break;
+      case 13: launch_band<13, 8, R>(a, st); break;
+      case 17: launch_band<17, 8, R>(a, st); break;
+      default: return SNAP_EUNSUPPORTED;
+    }
+  } else if (alt == 1) {
+    switch (bb) {
+      case 1: launch_band<1, 8, R>(a, st); break;
+      case 2: launch_band<2, 8, R>(a, st); break;
+      case 3: launch_band<3, 8, R>(a, st); break;
+      case 5: launch_band<5, 8, R>(a, st); break;
+      case 7: launch_band<7, 8, R>(a, st); break;
+      case 9: launch_band<9, 8, R>(a, st); break;
+      default: return SNAP_EUNSUPPORTED;
+    }
+  } else {
+    return SNAP_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP;
 #endif
@@ -1088,10 +1113,24 @@ bool band_supported(int nx, int nt, bool mixed) {
   return nx >= 3 && nt >= 2 && pick_bb(band_bb(nx, nt)) > 0 && (int64_t)nx * nt < (1 << 30);
 }
 
-// Kernel class of a shape: the instantiated block half-bandwidth.
+// Kernel class of a shape: the instantiated block half-bandwidth, default
+// launch shape.
 int band_class(int nx, int nt) { return band_supported(nx, nt, false) ? pick_bb(band_bb(nx, nt)) : -1; }
 
-size_t band_workspace_bytes(int nx, int nt, bool mixed) {
+// Classes the autotuner may choose between for a class (default shape first).
+int band_variants(int cls, int* out, int cap) {
+  int n = 0;
+  if (cls < 0 || cap < 1) return 0;
+  cls %= kBandAlt;
+  out[n++] = cls;
+  if (cls <= 9 && n < cap) out[n++] = cls + kBandAlt;
+  return n;
+}
+
+// wavefronts per workgroup of a class (for plan descriptions)
+int band_waves(int cls) { return (cls % kBandAlt) <= 9 && cls / kBandAlt == 0 ? 4 : 8; }
+
+size_t band_workspace_bytes(int nx, int nt, bool mixed) {  // the same for every launch shape
   const int bb = pick_bb(band_bb(nx, nt));
   return ws_layout(nx, nt, bb, mixed ? sizeof(float) : sizeof(double)).total;
 }

@@ -36,8 +36,6 @@
 // the same sums already describe the new iterate, so it goes straight on to
 // the convergence test and the next solve.  Two workgroup barriers per Newton
 // iteration; halving (alpha < 1) falls back to explicit trial passes.
-#include <cstdlib>
-
 #include "snap_device.hpp"
 
 namespace snap {
@@ -701,27 +699,32 @@ int launch_index(const KernelArgs& a, int i, hipStream_t st) {
   return 0;
 }
 
-// class override for launch-shape sweeps: SNAP_SLAB_CLASS=<index>
-int forced_class() {
-  static const int v = [] {
-    const char* e = getenv("SNAP_SLAB_CLASS");
-    return e ? atoi(e) : -1;
-  }();
-  return v;
-}
-
 }  // namespace
 
 // Kernel class of an (nx, nt) shape: the first class whose grid capacity and
 // u_hat staging cover it; wider grids go to the wide-grid kernel.
 int slab_class(int nx, int nt) {
-  const int f = forced_class();
-  if (f >= 0 && f < kNumCfg && cfg_fits(kCfg[f], nx, nt)) return f;
   for (int i = 0; i < kNumCfg; ++i)
     if (cfg_fits(kCfg[i], nx, nt)) return i;
   const int wc = slab_wide_class(nx, nt);
   return wc < 0 ? -1 : kWideBase + wc;
 }
+
+// Classes the autotuner may choose between for a shape: every grouped class
+// whose capacity covers it (the default first), or the wide-grid class.
+int slab_variants(int nx, int nt, int* out, int cap) {
+  int n = 0;
+  const int d = slab_class(nx, nt);
+  if (d < 0 || cap < 1) return 0;
+  out[n++] = d;
+  if (d >= kWideBase) return n;
+  for (int i = 0; i < kNumCfg && n < cap; ++i)
+    if (i != d && cfg_fits(kCfg[i], nx, nt)) out[n++] = i;
+  return n;
+}
+
+// wavefronts per workgroup of a class (for plan descriptions)
+int slab_waves(int cls) { return cls >= kWideBase ? 8 : (cls >= 0 && cls < kNumCfg ? kCfg[cls].nw : 0); }
 
 // Host entry used by the plan: one workgroup per listed sample; every sample
 // of the launch belongs to kernel class `cls` (shapes may differ).
