@@ -451,7 +451,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
           if (k > p) rk -= lk * rp;
           if (lane < kT) Nl[k * kLd + p] = (k > p) ? lk : 0.0;
 #pragma unroll
-          for (int i = p + 1; i < kT; ++i) a[i] -= (lane_bcast(a[i], p) * rdp) * ap;
+          for (int i = p + 1; i < kT; ++i) a[i] -= lane_bcast(a[i], p) * lk;   // L[i][p] A[p][k]
         }
         if (lane < kT) {
           Nl[k * kLd + k] = 0.0;
