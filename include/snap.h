@@ -83,7 +83,7 @@ enum snap_flags {
                                 null stream the call runs its launches
                                 directly.  Calls with this flag on one plan
                                 from several host threads are serialized. */
-  SNAP_FLAG_AUTOTUNE = 4     /* snap_plan_create times every launch shape that
+  SNAP_FLAG_AUTOTUNE = 4,    /* snap_plan_create times every launch shape that
                                 can run a group of samples (lanes per time slab
                                 and rounds for the slab-row families; wavefronts
                                 sharing one sample's band window for the banded
@@ -96,6 +96,13 @@ enum snap_flags {
                                 shape changes the summation order of some
                                 reductions, so results may differ from the
                                 untuned plan's in the last bits. */
+  SNAP_FLAG_SOC = 8          /* slab-row families: when the full Newton step
+                                fails the merit test and raised the constraint
+                                violation, try one second-order correction
+                                q = p - W^{-1} J^T S^{-1} h(u + p) with the factor
+                                at u before halving.  Off by default: on strongly
+                                nonlinear Fisher-KPP samples it slowed or stalled
+                                convergence where plain backtracking did not. */
 };
 
 /* call-level return codes */

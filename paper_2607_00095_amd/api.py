@@ -11,7 +11,7 @@ import torch
 
 MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY = 1, 2, 3, 4
 PREC_FP64, PREC_MIXED = 0, 1
-FLAG_KEEP_FACTOR, FLAG_GRAPH, FLAG_AUTOTUNE = 1, 2, 4
+FLAG_KEEP_FACTOR, FLAG_GRAPH, FLAG_AUTOTUNE, FLAG_SOC = 1, 2, 4, 8
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 

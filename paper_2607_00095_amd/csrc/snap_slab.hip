@@ -171,6 +171,7 @@ struct SlabSh {
   double Td[kMaxNt], To[kMaxNt], r[kMaxNt], res[kMaxNt], dx[kMaxNt];
   double lamic[NXM], lampic[NXM], ric[NXM], gic[NXM];   // IC rows
   double red[16][4];     // per-wavefront partials: max|g|, p.p, (u-u_hat).p
+  double red2[16][2];    // second-order-correction trial: q.q, (u-u_hat).q
   double scal[4];        // IC rows: sum a_0 r_ic, max|h_ic|, sum|h_ic|
   int flag[4];           // done, accepted, backtrack, line-search verdict
 };
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   for (int it = 0; status != SNAP_ST_NONFINITE; ++it) {
     // ------------------------------------------------ wavefront 0: accept, test, solve
     if (w == 0) {
-      int done = 0, acc = 0, bt = 0;
+      int done = 0, acc = 0, bt = 0, soc = 0;
       // rows k = lane and lane + 64 (nr <= 127): h from the slab sums, once
       double hk[2];
 #pragma unroll
@@ -416,6 +417,9 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         const double dphi = dd - mu * h1cur;
         const double dphit = dd + 0.5 * pp + mu * (h1 - h1cur);
         acc = (dphit <= 1e-4 * dphi) || !(dphi < 0.0) || hinf <= 1e-6;
+        // rejected: a second-order correction is tried only when the full step
+        // increased the constraint violation (the curvature of h is what failed)
+        soc = (A.opt.flags & SNAP_FLAG_SOC) && !acc && h1 > h1cur;
         if (acc) {
 #pragma unroll
           for (int r = 0; r < RMAX; ++r)
@@ -524,10 +528,10 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           mu = fmax(mu, 1.1 * lm + 1e-8);
         }
       }
-      if (lane == 0) { sh.flag[0] = done; sh.flag[1] = acc; sh.flag[2] = bt; }
+      if (lane == 0) { sh.flag[0] = done; sh.flag[1] = acc; sh.flag[2] = bt | (soc << 1); }
     }
     lds_barrier();
-    const int done = sh.flag[0], acc = sh.flag[1], bt = sh.flag[2];
+    const int done = sh.flag[0], acc = sh.flag[1], bt = sh.flag[2] & 1, soc_try = sh.flag[2] >> 1;
     if (acc) {
       if (w != 0) {
 #pragma unroll
@@ -538,10 +542,134 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       ++iters;
     }
     if (bt) {
+      ++backtracks;   // the full step was rejected
+      // ---------------------------------------------- second-order correction
+      // One try before halving: with the Schur system still assembled at u
+      // (the factor is reused), solve S z = h(u + p) and move to
+      // u + q, q = p + p_soc, p_soc = -W^{-1} J(u)^T z; the same Armijo test
+      // (directional derivative of p) decides.
+      if (soc_try) {
+        if (w == 0) {
+          // IC rows at u + p (group 0); with the IC block eliminated the
+          // reduced right-hand side is h_k(u+p), minus sum_x a_0(x) h_ic(x) on row 0
+          double sar = 0.0;
+          if (grp == 0) {
+#pragma unroll
+            for (int j = 0; j < XPL; ++j) {
+              const int x = xat(j);
+              if (x < nx) {
+                const double hic = (u[0][j] + 1.0 * pst[0][j]) - sh.gic[x];
+                sh.ric[x] = hic;
+                sar += coef(0, u[0][j]) * hic;
+              }
+            }
+          }
+          sar = group_sum<G>(sar);
+          if (lane == G - 1) sh.scal[3] = sar;
+          wave_sync();
+          for (int k = lane; k < nr; k += kWave) sh.res[k] = row_h(k) - (k == 0 ? sh.scal[3] : 0.0);
+          wave_sync();
+          if (nr > 0) pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
+          const double z0 = nr > 0 ? sh.dx[0] : 0.0;
+          const double W0 = sh.W[0];
+          if (grp == 0) {
+#pragma unroll
+            for (int j = 0; j < XPL; ++j) {
+              const int x = xat(j);
+              if (x < nx) sh.ric[x] = W0 * sh.ric[x] - coef(0, u[0][j]) * z0;   // z_ic
+            }
+          }
+        }
+        lds_barrier();
+        // trial u + q: slab sums for h, the IC rows, and the merit terms of q
+        {
+          const int xs = opaque(sub), gq = opaque(grp), eb = opaque(base);
+          double qq = 0.0, dq = 0.0;
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) {
+            if (!live(r)) continue;
+            const int k = gq + NG * r;
+            const bool kv = k < nt;
+            const double zk = (k < nr) ? sh.dx[k] : 0.0;
+            const double zkm = (k >= 1 && kv) ? sh.dx[k - 1] : 0.0;
+            const double rW = kv ? sh.rW[k] : 1.0;
+            double Su = 0, Suu = 0, h1 = 0;
+#pragma unroll
+            for (int j = 0; j < XPL; ++j) {
+              const int x = xat(j);
+              if (kv && x < nx) {
+                const double uu = u[r][j];
+                const double zm = (r == 0 && k == 0) ? sh.ric[xs + G * j] : zkm;
+                const double q = pst[r][j] - (coef(k, uu) * zk + zm) * rW;
+                const double us = uu + q;
+                const double d = uu - uhl[eb + r * rstride + G * j];
+                qq += q * q;
+                dq += d * q;
+                Su += us; Suu += us * us;
+                if (r == 0 && k == 0) h1 += fabs(us - sh.gic[xs + G * j]);
+              }
+            }
+            Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
+            if (glast && kv) { sh.S1[k] = Su; sh.S2[k] = Su - Suu; }
+            if (w == 0 && r == 0) {
+              h1 = group_sum<G>(h1);
+              if (lane == G - 1) sh.scal[2] = h1;
+            }
+          }
+          qq = wave_sum(qq); dq = wave_sum(dq);
+          if (lane == 0) { sh.red2[w][0] = qq; sh.red2[w][1] = dq; }
+        }
+        lds_barrier();
+        if (w == 0) {
+          double dd = 0.0, qq = 0.0, dq = 0.0;
+          for (int q = 0; q < NW; ++q) { dd += sh.red[q][2]; qq += sh.red2[q][0]; dq += sh.red2[q][1]; }
+          const double dphi = dd - mu * h1cur;
+          const double dphis = dq + 0.5 * qq + mu * (h1_rows() - h1cur);
+          const int good = (dphis <= 1e-4 * dphi) ? 1 : 0;
+          if (lane == 0) sh.flag[3] = good;
+        }
+        lds_barrier();
+        if (sh.flag[3]) {
+          // accept u + q with lam+ (the multipliers of the full step)
+          const int xs = opaque(sub), gq = opaque(grp);
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) {
+            const int k = gq + NG * r;
+            const bool kv = k < nt;
+            const double zk = (k < nr) ? sh.dx[k] : 0.0;
+            const double zkm = (k >= 1 && kv) ? sh.dx[k - 1] : 0.0;
+            const double rW = kv ? sh.rW[k] : 1.0;
+#pragma unroll
+            for (int j = 0; j < XPL; ++j) {
+              const int x = xat(j);
+              if (kv && x < nx) {
+                const double uu = u[r][j];
+                const double zm = (r == 0 && k == 0) ? sh.ric[xs + G * j] : zkm;
+                u[r][j] = uu + (pst[r][j] - (coef(k, uu) * zk + zm) * rW);
+              }
+            }
+          }
+          lds_barrier();   // every lane has read z and the IC correction
+          for (int k = tid; k < nr; k += NT) {
+            const double l = sh.lamp[k];
+            const double wk = wslab(k, l);
+            sh.lam[k] = l;
+            sh.W[k] = wk;
+            sh.rW[k] = rcp_nr(wk);
+          }
+          for (int x = tid; x < nx; x += NT) sh.lamic[x] = sh.lampic[x];
+          ++iters;
+          lds_barrier();
+          sums_pass(sh.lam, sh.lamic, false);
+          lds_barrier();
+          pend = false;
+          continue;
+        }
+        ++backtracks;   // the corrected step was rejected too
+      }
       // ---------------------------------------------- backtracking (alpha < 1)
       double alpha = 1.0;
       int ok = 0;
-      ++backtracks;
       for (int ls = 1; ls <= A.opt.max_ls; ++ls) {
         alpha *= 0.5;
         const int xs = opaque(sub), gq = opaque(grp);

@@ -38,3 +38,21 @@ def test_backtracking_reaches_oracle_point(precision, tol):
     u_o, lam_o, _ = project_batch(b)
     for s, o in zip(b.samples, b.var_off):
         assert rel_err(res["u_np"][o:o + s.n], u_o[o:o + s.n]) <= tol
+
+
+# samples on which the one-try second-order correction is taken and the
+# iteration still converges (on the others it slows or stalls convergence,
+# which is why it is off by default)
+SOC_PICKS = [PICKS[1], PICKS[3], PICKS[4]]
+
+
+def test_second_order_correction_option():
+    smp = [synthgen.fisher_kpp_batch(batch=4, nx=20, nt=8, seed=s, dt=dt).samples[i]
+           for dt, s, i in SOC_PICKS]
+    b = synthgen.Batch(smp, name="fisher_kpp").pack()
+    res = gpu_project(b, snap.Options(flags=snap.FLAG_SOC))
+    st = res["stats"]
+    assert (st["status"] == 0).all(), st["status"]
+    u_o, _, _ = project_batch(b)
+    for s, o in zip(b.samples, b.var_off):
+        assert rel_err(res["u_np"][o:o + s.n], u_o[o:o + s.n]) <= 1e-10
