@@ -185,7 +185,7 @@ struct SlabLds {
   double uhl[UHN];   // u_hat (forward) or u* + grad_u (adjoint)
 };
 
-template <int NW, int G, int XPL, int RMAX, int UHN, typename TS>
+template <int NW, int G, int XPL, int RMAX, int UHN, typename TS, bool SOC>
 __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   constexpr int NT = NW * kWave;   // threads
   constexpr int NG = NT / G;       // slab groups per round
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         acc = (dphit <= 1e-4 * dphi) || !(dphi < 0.0) || hinf <= 1e-6;
         // rejected: a second-order correction is tried only when the full step
         // increased the constraint violation (the curvature of h is what failed)
-        soc = (A.opt.flags & SNAP_FLAG_SOC) && !acc && h1 > h1cur;
+        soc = SOC && !acc && h1 > h1cur;
         if (acc) {
 #pragma unroll
           for (int r = 0; r < RMAX; ++r)
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       // (the factor is reused), solve S z = h(u + p) and move to
       // u + q, q = p + p_soc, p_soc = -W^{-1} J(u)^T z; the same Armijo test
       // (directional derivative of p) decides.
-      if (soc_try) {
+      if (SOC && soc_try) {
         if (w == 0) {
           // IC rows at u + p (group 0); with the IC block eliminated the
           // reduced right-hand side is h_k(u+p), minus sum_x a_0(x) h_ic(x) on row 0
@@ -809,11 +809,17 @@ bool cfg_fits(const SlabCfg& f, int nx, int nt) {
          nt <= (f.nw * kWave / f.g) * f.rmax && nx * nt <= f.uhn;
 }
 
+// the second-order-correction try (SNAP_FLAG_SOC) is built into its own
+// instantiation, so the default kernel carries none of its registers
 template <int I, typename TS>
 void launch_cfg(const KernelArgs& a, hipStream_t st) {
   constexpr SlabCfg f = kCfg[I];
-  hipLaunchKernelGGL((slab_kernel<f.nw, f.g, f.xpl, f.rmax, f.uhn, TS>), dim3(a.count),
-                     dim3(f.nw * kWave), 0, st, a);
+  if (a.opt.flags & SNAP_FLAG_SOC)
+    hipLaunchKernelGGL((slab_kernel<f.nw, f.g, f.xpl, f.rmax, f.uhn, TS, true>), dim3(a.count),
+                       dim3(f.nw * kWave), 0, st, a);
+  else
+    hipLaunchKernelGGL((slab_kernel<f.nw, f.g, f.xpl, f.rmax, f.uhn, TS, false>), dim3(a.count),
+                       dim3(f.nw * kWave), 0, st, a);
 }
 
 template <typename TS>
