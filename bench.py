@@ -50,6 +50,24 @@ KERNEL_NAMES = {
 }
 
 
+BAND_BBS = (1, 2, 3, 5, 7, 9, 13, 17)
+
+
+def factor_bytes(batch, elem=8):
+    """Bytes of the stored band factor (16x16 blocks, BB+1 per block panel) of
+    the batch's banded samples: what one substitution sweep reads."""
+    tot = 0
+    for s in batch.samples:
+        if int(s.family) != 3:
+            continue
+        b = s.nx + 2 if s.nt > 2 else 4
+        need = (max(b, 4) + 15) // 16
+        bb = next(x for x in BAND_BBS if x >= need)
+        nb = (s.nx * (s.nt - 1) + 15) // 16
+        tot += nb * (bb + 1) * 256 * elem
+    return tot
+
+
 def source_hash(path):
     with open(os.path.join(ROOT, path), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -243,6 +261,13 @@ def main():
         secb = time_calls(lambda: snap.project_backward(plank, uk, lk, aux, wsk, grad, gout, stb, stream),
                           args.steps, args.warmup, stream)
         out["backward"] = {"value": B / secb, "ms_per_step": secb * 1e3, "unit": "samples/s"}
+        fb = factor_bytes(batch)
+        if fb:
+            # the adjoint of the banded samples is one forward and one backward
+            # substitution sweep over the kept factor: it streams the factor twice
+            out["backward"]["factor_stream"] = {
+                "bytes": 2 * fb, "achieved": 2 * fb / secb / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": 2 * fb / secb / 1e9 / HBM_PEAK_GBS}
 
         # batched form: launch shapes picked by the plan's autotuner, the whole
         # launch sequence replayed from a HIP graph (needs a non-null stream)
