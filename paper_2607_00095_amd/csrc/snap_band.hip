@@ -752,7 +752,7 @@ __device__ void to_internal(const Ctx& C, const double* canon, double* rin) {
 template <int BB, int NW, typename R>
 __device__ __attribute__((always_inline)) int solve_with_factor(
     const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, bool have_y, double* x,
-    int max_refine = 6) {
+    int max_refine = 6, double abs_floor = 0.0) {
   double* Y = (double*)(C.ws + WL.Y);
   double* rin = (double*)(C.ws + WL.rin);
   double* res = (double*)(C.ws + WL.res);
@@ -775,7 +775,7 @@ __device__ __attribute__((always_inline)) int solve_with_factor(
     }
     if (plain || it == max_refine) break;
     const double rm = schur_residual<NW>(C, WL, x, res, sh.red);
-    if (!(rm > 1e-13 * rn)) break;
+    if (!(rm > fmax(1e-13 * rn, abs_floor))) break;
     to_internal<NW>(C, res, rin);
   }
   return refines;
@@ -929,7 +929,9 @@ SNAP_BAND_KERNEL void band_solve(KernelArgs A) {
   // explicit float64 refinement is applied only in the local phase, where the
   // float32 error would otherwise limit the last digits.
   const int max_ref = S->hinf <= 1e-6 ? 6 : 0;
-  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, true, lamp, max_ref);
+  // a Newton step only needs its Schur residual well below the feasibility
+  // tolerance (the next evaluation re-forms h in float64)
+  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, true, lamp, max_ref, 0.1 * A.opt.tol_h);
   for (int r = threadIdx.x; r < C.m; r += NW * kWave) lamp[r] += C.lam[r];
   if (threadIdx.x == 0) S->refines += refines;
 }
