@@ -18,8 +18,9 @@
 // retiring panel block is replaced in place by the entering block of row
 // J+BB+1.  Per panel J:
 //   1. the diagonal block is factored in registers by one wavefront (lane k
-//      holds column k; pivot columns are broadcast lane to lane), giving D_J,
-//      L_JJ^{-1}, T = L_JJ^{-T} D_J^{-1} and the forward-substitution block;
+//      holds column k, lane 16 + k column k of the identity; pivot columns are
+//      broadcast lane to lane and both apply the same row operations), giving
+//      D_J, L_JJ^{-1}, T = L_JJ^{-T} D_J^{-1} and the forward-substitution block;
 //   2. panel blocks L(I,J) = S(I,J) T   (MFMA);
 //   3. trailing update S(I,K) -= L(I,J) D_J L(K,J)^T   (MFMA, rank 16);
 //   4. the entering block row is assembled from the stencil (S is never
@@ -78,8 +79,7 @@ struct BandShared {
   R P[BB + 1][kTL];        // panel blocks (S, then L after the panel solve)
   R NR[BB + 1][kTL];       // staging area of the entering block row
   R T[kTL];                // L_JJ^{-T} D_J^{-1}
-  double Xw[kTL];          // L_JJ^{-1} (solves); strictly lower L_JJ (factor)
-  double Wk[3][kTL];       // powers of the strictly lower part of L_JJ
+  double Xw[kTL];          // L_JJ^{-1} (solves)
   double Dv[kT];
   double rD[kT];           // 1 / D_J
   double ring[(BB + 1) * kT];   // right-hand side / solution window of live block rows
@@ -424,97 +424,46 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
 
     // (b) wavefront 0: LDL^T of the diagonal block; wavefront 1: next block row
     if (w == 0) {
-      // LDL^T of the symmetric 16x16 diagonal block in registers.  Lane k
-      // (k = lane mod 16; the four rows of the wavefront compute alike) holds
-      // column k of the working matrix, a[i] = A[i][k], and entry k of the
-      // right-hand side.  Pivot p broadcasts column p from lane p and applies
-      // its row operations to A and to the right-hand side (y = L^{-1} r); the
-      // multipliers fill the strictly lower part N of L = I + N in LDS.
+      // LDL^T of the symmetric 16x16 diagonal block in registers.  Lanes
+      // 0..15 hold column k = lane of the working matrix (v[i] = A[i][k]) and
+      // entry k of the right-hand side; lanes 16..31 hold column k = lane - 16 of
+      // the identity.  Pivot p broadcasts column p from lane p and every lane
+      // applies the same row operation v[i] -= (A[i][p] / D_p) v[p], so the
+      // matrix lanes eliminate (the right-hand side becomes y = L^{-1} r) while
+      // the identity lanes turn into the columns of X = L^{-1}.  Row p of X is
+      // final after pivot p: T = L^{-T} D^{-1} and the stored X are written as
+      // the sweep goes.  (Lanes 32..63 repeat lanes 0..31.)
       const int k = lane & (kT - 1);
-      double* Nl = sh.Xw;
+      const bool xl = (lane & 16) != 0;        // an identity / X lane
       double dmine = 1.0;
       int nonpos = 0;
-      {
-        double a[kT];
+      double v[kT];
 #pragma unroll
-        for (int i = 0; i < kT; ++i) a[i] = (double)sh.P[0][i * kLd + k];
-        double rk = sh.ring[(J % (BB + 1)) * kT + k];
+      for (int i = 0; i < kT; ++i) v[i] = xl ? (i == k ? 1.0 : 0.0) : (double)sh.P[0][i * kLd + k];
+      double rk = sh.ring[(J % (BB + 1)) * kT + k];
+      R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
 #pragma unroll
-        for (int p = 0; p < kT; ++p) {
-          const double dp = lane_bcast(a[p], p);   // A[p][p]
-          nonpos |= !(dp > 0.0);
-          const double rdp = rcp_nr(dp);
-          if (k == p) dmine = dp;
-          const double ap = a[p];
-          const double lk = ap * rdp;              // L[k][p] = A[p][k] / D_p (symmetry)
-          const double rp = lane_bcast(rk, p);
-          if (k > p) rk -= lk * rp;
-          if (lane < kT) Nl[k * kLd + p] = (k > p) ? lk : 0.0;
+      for (int p = 0; p < kT; ++p) {
+        const double dp = lane_bcast(v[p], p);   // A[p][p]
+        nonpos |= !(dp > 0.0);
+        const double rdp = rcp_nr(dp);
+        if (k == p) dmine = dp;
+        const double m = v[p] * rdp;             // A lanes: L[k][p] = A[p][k] / D_p (symmetry)
+        const double rp = lane_bcast(rk, p);
+        if (k > p) rk -= m * rp;
 #pragma unroll
-          for (int i = p + 1; i < kT; ++i) a[i] -= lane_bcast(a[i], p) * lk;   // L[i][p] A[p][k]
-        }
-        if (lane < kT) {
-          Nl[k * kLd + k] = 0.0;
-          sh.Dv[k] = dmine;
-          sh.rD[k] = rcp_nr(dmine);
-          Dg[(size_t)J * kT + k] = dmine;
-          sh.yJ[k] = rk;
-          Y[(size_t)J * kT + k] = rk;
+        for (int i = p + 1; i < kT; ++i) v[i] -= lane_bcast(v[i], p) * m;
+        if (xl && lane < 32) {                   // row p of X is final
+          sh.T[k * kLd + p] = (R)(v[p] * rdp);   // T[k][p] = X[p][k] / D_p
+          Lgd[p * kT + k] = (R)v[p];
         }
       }
-      wave_sync();
-      // X = L^{-1} = (I - N)(I + N^2)(I + N^4)(I + N^8), N^16 = 0: six 16x16
-      // products on the matrix cores instead of a 16-step substitution.
-      {
-        using M = Mfma<double>;
-        const int li = lane & 15, lg = lane >> 4;
-        auto mm = [&](const double* A_, const double* B_) {
-          M::V c = M::V{0, 0, 0, 0};
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq)
-            c = M::mma(A_[li * kLd + 4 * qq + lg], B_[(4 * qq + lg) * kLd + li], c);
-          return c;
-        };
-        auto put = [&](double* D_, const M::V& c) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) D_[M::row(lg, e) * kLd + li] = c[e];
-        };
-        double* N2 = sh.Wk[0];
-        double* N4 = sh.Wk[1];
-        double* N8 = sh.Wk[2];
-        put(N2, mm(Nl, Nl));
-        wave_sync();
-        put(N4, mm(N2, N2));
-        wave_sync();
-        put(N8, mm(N4, N4));
-        M::V q = mm(Nl, N2);                     // N N^2
-        // Q1 = (I - N)(I + N^2) = I - N + N^2 - N^3, kept in the register layout
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = M::row(lg, e);
-          q[e] = (r == li ? 1.0 : 0.0) - Nl[r * kLd + li] + N2[r * kLd + li] - q[e];
-        }
-        wave_sync();
-        double* Q = N2;                          // N^2 is no longer needed
-        put(Q, q);
-        wave_sync();
-        M::V t = mm(Q, N4);                      // Q2 = Q1 (I + N^4)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) t[e] += q[e];
-        wave_sync();
-        put(Q, t);
-        wave_sync();
-        M::V x = mm(Q, N8);                      // X = Q2 (I + N^8)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) x[e] += t[e];
-        // T[j][r] = X[r][j] / D_r and the stored X, from the result layout
-        R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = M::row(lg, e);
-          sh.T[li * kLd + r] = (R)(x[e] * sh.rD[r]);
-          Lgd[r * kT + li] = (R)x[e];
-        }
+      if (lane < kT) {
+        sh.Dv[k] = dmine;
+        sh.rD[k] = rcp_nr(dmine);
+        Dg[(size_t)J * kT + k] = dmine;
+        sh.yJ[k] = rk;
+        Y[(size_t)J * kT + k] = rk;
       }
       if (lane == 0 && nonpos) sh.flag[0] = 1;
     } else if (w == 1 && lane < kT) {
