@@ -490,8 +490,11 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
               resmax = wave_max(resmax);
               wave_sync();
               // a Newton step only needs its residual well below the feasibility
-              // tolerance; the adjoint is solved to the working precision
-              if (!(resmax > fmax(1e-15 * rn, bwd ? 0.0 : 0.1 * A.opt.tol_h))) break;
+              // tolerance, and far from the solution (||h||_inf > 1e-6) only a
+              // good descent direction; the adjoint is solved to working precision
+              const double target = bwd ? 1e-15 * rn
+                                        : (hinf > 1e-6 ? 1e-6 * rn : fmax(1e-15 * rn, 0.1 * A.opt.tol_h));
+              if (!(resmax > target)) break;
               pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
               for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.dx[k];
               wave_sync();

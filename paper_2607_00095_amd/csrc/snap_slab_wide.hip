@@ -315,7 +315,9 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_wide_kernel(KernelArgs A
             }
             resmax = wave_max(resmax);
             wave_sync();
-            if (!(resmax > fmax(1e-15 * rn, bwd ? 0.0 : 0.1 * A.opt.tol_h))) break;
+            const double target = bwd ? 1e-15 * rn
+                                      : (hinf > 1e-6 ? 1e-6 * rn : fmax(1e-15 * rn, 0.1 * A.opt.tol_h));
+            if (!(resmax > target)) break;
             pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
             for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.dx[k];
             wave_sync();
