@@ -137,6 +137,34 @@ def time_calls(fn, steps, warmup, stream):
     return start.elapsed_time(stop) / 1e3 / steps   # seconds per call
 
 
+def sweep(args):
+    """Forward time of the plain FP64 and mixed forms against batch size, with
+    the workload's shapes (seeded samples of the same generator)."""
+    import torch
+    import paper_2607_00095_amd as snap
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    for B in (1, 8, 32, 128, 512, 2048):
+        batch = synthgen.make(args.workload, batch=B)
+        uhat = torch.from_numpy(batch.uhat).to(dev)
+        aux = torch.from_numpy(batch.aux).to(dev)
+        row = {"workload": args.workload, "batch": B}
+        for label, prec in (("fp64", snap.PREC_FP64), ("mixed", snap.PREC_MIXED)):
+            plan = snap.Plan.from_batch(batch, snap.Options(precision=prec))
+            ws = plan.new_workspace()
+            u = torch.empty(plan.total_vars, dtype=torch.float64, device=dev)
+            lam = torch.empty(max(plan.total_rows, 1), dtype=torch.float64, device=dev)
+            st = torch.empty(B * 32, dtype=torch.uint8, device=dev)
+            steps = max(2, min(args.steps, 20))
+            sec = time_calls(lambda: snap.project(plan, uhat, aux, ws, u, lam, st, stream),
+                             steps, max(1, args.warmup), stream)
+            ok = int((snap.stats_to_numpy(st, B)["status"] == 0).sum())
+            row[label] = {"ms_per_call": sec * 1e3, "samples_per_s": ok / sec, "converged": ok}
+            del plan, ws
+            torch.cuda.empty_cache()
+        print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +176,8 @@ def main():
                     help="time the FP64 forward only (for profiler runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 512 MiB device-to-device 5 times (calibrates HBM byte counters)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="forward time against batch size (1 .. 2048) for the workload; one JSON line per size")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -162,6 +192,10 @@ def main():
         print("bench.py measures one GPU: every sample is independent and the library has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.sweep:
+        sweep(args)
+        return
 
     name = args.workload
     spec = dict(synthgen.CONFIGS[name]["kw"])
