@@ -48,6 +48,13 @@ namespace {
 constexpr int kMaxNt = 128;
 constexpr double kWFloor = 0.1;
 
+// kinds of slab-sum pass (see the kernel)
+constexpr int kPoint = 0, kStep = 1, kStart = 2;
+template <int K>
+struct PassKind {
+  static constexpr int value = K;
+};
+
 template <typename TS>
 struct PcrBuf {
   TS a[2][kWave], c[2][kWave], d[2][kWave], rb[2][kWave];
@@ -171,8 +178,9 @@ struct SlabSh {
   double Td[kMaxNt], To[kMaxNt], r[kMaxNt], res[kMaxNt], dx[kMaxNt];
   double lamic[NXM], lampic[NXM], ric[NXM], gic[NXM];   // IC rows
   double red[16][4];     // per-wavefront partials: max|g|, p.p, (u-u_hat).p
-  double red2[16][2];    // second-order-correction trial: q.q, (u-u_hat).q
-  double scal[4];        // IC rows: sum a_0 r_ic, max|h_ic|, sum|h_ic|
+  double red2[16][2];    // load: max|u_hat|, non-finite; second-order trial: q.q, (u-u_hat).q
+  double scal[6];        // IC rows: sum a_0 r_ic, max|h_ic|, sum|h_ic|; [3] second-order
+                         // sum a_0 h_ic; [4] dlam_0 of the pending step; [5] max|lam+_ic|
   int flag[4];           // done, accepted, backtrack, line-search verdict
 };
 
@@ -283,28 +291,26 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     sh.lam[k] = 0.0;
     sh.lamp[k] = 0.0;
   }
-  {
-    const double mx = wave_max(umax);
-    const int nf = __any(nonfinite) ? 1 : 0;
-    if (lane == 0) { sh.red[w][0] = mx; sh.red[w][1] = (double)nf; }
-  }
-  lds_barrier();
-  double uscale = 0.0, nfin = 0.0;
-  for (int q = 0; q < NW; ++q) { uscale = fmax(uscale, sh.red[q][0]); nfin += sh.red[q][1]; }
-  uscale += 1.0;
-  lds_barrier();
-
-  // Slab sums at the point u + alpha*p with multipliers lamv (slab rows) and
-  // lamicv (IC rows): sum u, sum u^2, sum g, sum u g per slab, and the IC
-  // rows' r_ic = h_ic - g/W_0 (W_0 of those multipliers).  With STEP the
-  // step p is first formed at the current point with lam+ (into pst), and
-  // the merit terms p.p and (u - u_hat).p are accumulated.
-  auto sums_pass = [&](const double* lamv, const double* lamicv, bool step) {
+  // Slab sums at a point, in one of three forms (the pass kind is a
+  // compile-time constant, so each call site gets its own code):
+  //   kPoint  the point u with multipliers lamv (slab rows), lamicv (IC rows);
+  //   kStep   first the step p at the current point with lam+ (into pst),
+  //           with the merit terms p.p and (u - u_hat).p, then the trial
+  //           point u + p; the IC rows' lam+ is formed here, by the lanes that
+  //           own slab 0 (lam+_ic = lam_ic + W_0 r_ic - a_0 dlam_0, stored
+  //           for the line search and its maximum kept for the penalty);
+  //   kStart  the forward start u = u_hat, lam = 0, where g = 0 exactly, so
+  //           only sum u and sum u^2 are formed and nothing is read from LDS.
+  // Per slab: sum u, sum u^2, sum g, sum u g, and the IC rows'
+  // r_ic = h_ic - g/W_0 (W_0 of the multipliers the sums describe).
+  auto sums_pass = [&](const double* lamv, const double* lamicv, auto kind) {
+    constexpr int M = decltype(kind)::value;
+    constexpr bool step = M == kStep;
     const int eb = opaque(base), xs = opaque(sub), gq = opaque(grp);
     double st = 0.0, pp = 0.0, dd = 0.0;
     // W_0 at the point the sums describe: of lam+ at a trial point, else the
     // stored one (the adjoint keeps W of lam* while its multipliers are zero)
-    const double rW0 = step ? rcp_nr(wslab(0, nr > 0 ? lamv[0] : 0.0)) : sh.rW[0];
+    const double rW0 = step ? rcp_nr(wslab(0, nr > 0 ? lamv[0] : 0.0)) : (M == kStart ? 1.0 : sh.rW[0]);
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
       if (!live(r)) continue;
@@ -314,20 +320,31 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       // per-slab constants: a = a0 + a1 u on law slabs (0 on the last slab);
       // the +1 coefficient of row k-1 on slab k, or the IC multiplier on slab 0
       const double a0 = law ? a0c : 0.0, a1 = law ? a1c : 0.0;
-      const double lk = law ? lamv[k] : 0.0;
-      const double lkm = (k >= 1 && kv) ? lamv[k - 1] : 0.0;
+      const double lk = (law && M != kStart) ? lamv[k] : 0.0;
+      const double lkm = (k >= 1 && kv && M != kStart) ? lamv[k - 1] : 0.0;
       const bool ic = r == 0 && k == 0;
       // step at the current point: W of the current multipliers
-      const double rWc = kv ? sh.rW[k] : 1.0;
-      double Su = 0, Suu = 0, Sg = 0, Sug = 0, sar = 0, hmx = 0, h1 = 0;
+      const double rWc = (kv && step) ? sh.rW[k] : 1.0;
+      const double W0 = (ic && step) ? sh.W[0] : 0.0;
+      const double dl0 = (ic && step) ? sh.scal[4] : 0.0;
+      double Su = 0, Suu = 0, Sg = 0, Sug = 0, sar = 0, hmx = 0, h1 = 0, lpm = 0;
 #pragma unroll
       for (int j = 0; j < XPL; ++j) {
         const int x = xat(j);
         if (kv && x < nx) {
           double uu = u[r][j];
-          const double uh = uhl[eb + r * rstride + G * j];
-          const double lm = ic ? lamicv[xs + G * j] : lkm;
-          if (step) {
+          const double uh = M == kStart ? uu : uhl[eb + r * rstride + G * j];
+          double lm = lkm;
+          if (ic) {
+            if constexpr (step) {
+              lm = sh.lamic[xs + G * j] + (W0 * sh.ric[xs + G * j] - (a0 + a1 * uu) * dl0);
+              sh.lampic[xs + G * j] = lm;
+              lpm = fmax(lpm, fabs(lm));
+            } else {
+              lm = M == kStart ? 0.0 : lamicv[xs + G * j];
+            }
+          }
+          if constexpr (step) {
             const double d = uu - uh;
             const double jt = d + (a0 + a1 * uu) * lk + lm;
             const double p = -jt * rWc;
@@ -337,11 +354,16 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
             uu = uu + 1.0 * p;
           }
           const double a = a0 + a1 * uu;
-          const double g = (uu - uh) + a * lk + lm;
-          Su += uu; Suu += uu * uu; Sg += g; Sug += uu * g;
-          st = fmax(st, fabs(g));
+          Su += uu; Suu += uu * uu;
+          double g = 0.0;
+          if constexpr (M != kStart) {
+            g = (uu - uh) + a * lk + lm;
+            Sg += g; Sug += uu * g;
+            st = fmax(st, fabs(g));
+          }
           if (ic) {
-            const double hic = bwd ? 0.0 : uu - sh.gic[xs + G * j];
+            const double gi = M == kStart ? aux[xs + G * j] : sh.gic[xs + G * j];
+            const double hic = bwd ? 0.0 : uu - gi;
             const double ric = hic - g * rW0;
             sh.ric[xs + G * j] = ric;
             sar += a * ric;
@@ -351,7 +373,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         }
       }
       Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
-      Sg = group_sum<G>(Sg); Sug = group_sum<G>(Sug);
+      if constexpr (M != kStart) { Sg = group_sum<G>(Sg); Sug = group_sum<G>(Sug); }
       if (glast && kv) {
         const double cnt = (double)nx;
         sh.S1[k] = Su; sh.S2[k] = Su - Suu; sh.Sd[k] = Sg;
@@ -361,7 +383,11 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       }
       if (w == 0 && r == 0) {   // group 0 holds slab 0 and the IC rows
         sar = group_sum<G>(sar); h1 = group_sum<G>(h1); hmx = group_max<G>(hmx);
-        if (lane == G - 1) { sh.scal[0] = sar; sh.scal[1] = hmx; sh.scal[2] = h1; }
+        if constexpr (step) lpm = group_max<G>(lpm);
+        if (lane == G - 1) {
+          sh.scal[0] = sar; sh.scal[1] = hmx; sh.scal[2] = h1;
+          if constexpr (step) sh.scal[5] = lpm;
+        }
       }
       // one round at a time: bounds the values in flight
       __builtin_amdgcn_sched_barrier(0);
@@ -370,6 +396,19 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     if (step) { pp = wave_sum(pp); dd = wave_sum(dd); }
     if (lane == 0) { sh.red[w][0] = st; sh.red[w][1] = pp; sh.red[w][2] = dd; }
   };
+
+  // the forward's first sums come from the registers just loaded, before the
+  // first barrier (they touch no LDS that the set-up above writes)
+  if (!bwd) sums_pass(sh.lam, sh.lamic, PassKind<kStart>{});
+  {
+    const double mx = wave_max(umax);
+    const int nf = __any(nonfinite) ? 1 : 0;
+    if (lane == 0) { sh.red2[w][0] = mx; sh.red2[w][1] = (double)nf; }
+  }
+  lds_barrier();
+  double uscale = 0.0, nfin = 0.0;
+  for (int q = 0; q < NW; ++q) { uscale = fmax(uscale, sh.red2[q][0]); nfin += sh.red2[q][1]; }
+  uscale += 1.0;
 
   // feasibility row k from the slab sums S1, S2
   auto row_h = [&](int k) -> double {
@@ -383,13 +422,14 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   };
 
   double mu = 0.0, hinf = 0.0, stinf = 0.0, h1cur = 0.0;
+  double lmrow = 0.0;   // max |lam+| over the slab rows of the pending step (wavefront 0)
   int iters = 0, backtracks = 0, refines = 0, status = SNAP_ST_MAX_ITER;
   if (nfin > 0.0) status = SNAP_ST_NONFINITE;
   const int max_it = bwd ? 1 : A.opt.max_newton;
   bool pend = false;   // the sums describe the trial point u + p of a pending step
 
-  if (status != SNAP_ST_NONFINITE) {
-    sums_pass(sh.lam, sh.lamic, false);
+  if (bwd && status != SNAP_ST_NONFINITE) {
+    sums_pass(sh.lam, sh.lamic, PassKind<kPoint>{});
     lds_barrier();
   }
 
@@ -408,6 +448,9 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       h1 += fabs(hk[0]) + fabs(hk[1]);
       h1 = wave_sum(h1);
       if (pend) {
+        // penalty mu >= 1.1 ||lam+||_inf of the pending step (IC rows' part
+        // from the trial pass)
+        mu = fmax(mu, 1.1 * fmax(lmrow, sh.scal[5]) + 1e-8);
         // Armijo test of phi = 1/2||u - u_hat||^2 + mu||h||_1 at alpha = 1; the
         // change is formed from differences, d.p + p.p/2 + mu(||h_t||_1 - ||h||_1),
         // so rounding of the large sums in phi never decides.  Local phase
@@ -503,23 +546,11 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           }
         }
         if (!done) {
-          // sh.lamp holds dlam; IC multipliers from the eliminated block, then
-          // lam+ = lam + dlam, and the penalty mu >= 1.1 ||lam+||_inf
+          // sh.lamp holds dlam: keep dlam_0 for the IC rows' multipliers (formed
+          // from the eliminated block by the next pass), then lam+ = lam + dlam
           const double l0 = nr > 0 ? sh.lamp[0] : 0.0;
-          const double W0 = sh.W[0];
+          if (lane == 0) sh.scal[4] = l0;
           double lm = 0.0;
-          if (grp == 0) {
-#pragma unroll
-            for (int j = 0; j < XPL; ++j) {
-              const int x = xat(j);
-              if (x < nx) {
-                const double lpi = sh.lamic[x] + (W0 * sh.ric[x] - coef(0, u[0][j]) * l0);
-                sh.lampic[x] = lpi;
-                lm = fmax(lm, fabs(lpi));
-              }
-            }
-          }
-          wave_sync();
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int k = lane + kWave * e;
@@ -529,8 +560,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
               lm = fmax(lm, fabs(l));
             }
           }
-          lm = wave_max(lm);
-          mu = fmax(mu, 1.1 * lm + 1e-8);
+          lmrow = wave_max(lm);
         }
       }
       if (lane == 0) { sh.flag[0] = done; sh.flag[1] = acc; sh.flag[2] = bt | (soc << 1); }
@@ -665,7 +695,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           for (int x = tid; x < nx; x += NT) sh.lamic[x] = sh.lampic[x];
           ++iters;
           lds_barrier();
-          sums_pass(sh.lam, sh.lamic, false);
+          sums_pass(sh.lam, sh.lamic, PassKind<kPoint>{});
           lds_barrier();
           pend = false;
           continue;
@@ -731,7 +761,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       for (int x = tid; x < nx; x += NT) sh.lamic[x] += alpha * (sh.lampic[x] - sh.lamic[x]);
       ++iters;
       lds_barrier();
-      sums_pass(sh.lam, sh.lamic, false);
+      sums_pass(sh.lam, sh.lamic, PassKind<kPoint>{});
       lds_barrier();
       pend = false;
       continue;
@@ -755,7 +785,8 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           const int x = xat(j);
           if (k < nt && x < nx) {
             const double uu = u[r][j];
-            const double lic = (r == 0 && k == 0) ? sh.lampic[x] : 0.0;
+            // IC rows: lam_ic = 0, so the increment is W_0 r_ic - a_0 dlam_0
+            const double lic = (r == 0 && k == 0) ? sh.W[0] * sh.ric[x] - coef(0, uu) * sh.scal[4] : 0.0;
             const int e = eidx_from(eb, r, j);
             const double jt = (uu - uhl[e]) + coef(k, uu) * lk + lkm + lic;
             A.grad_uhat[vo + e] = -jt * rW;
@@ -766,7 +797,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       break;
     }
     // ------------------------------------------------ step and trial point at alpha = 1
-    sums_pass(sh.lamp, sh.lampic, true);
+    sums_pass(sh.lamp, sh.lampic, PassKind<kStep>{});
     lds_barrier();
     pend = true;
   }
