@@ -138,6 +138,15 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   wave_sync();
 }
 
+// max(a, |b|) in one instruction.  The compiler's fmax first quiets a
+// possible signalling NaN in `a` with an extra max; the running maxima here
+// only ever hold results of arithmetic, which are never signalling.
+__device__ __forceinline__ double max_abs(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Sum over each aligned group of G lanes (G a power of two <= 64): an
 // inclusive DPP scan (row_shr 1/2/4/8 inside rows of 16 lanes, then
 // row_bcast 15/31 across rows).  The LAST lane of every group ends holding
@@ -199,7 +208,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   constexpr int NG = NT / G;       // slab groups per round
   constexpr int GPW = kWave / G;   // groups per wavefront
   constexpr int NXM = G * XPL;     // widest grid of the class
-  static_assert(NW <= 16 && G <= kWave && NG * RMAX <= kMaxNt, "slab class");
+  static_assert(NW <= 16 && G <= kWave && NG * RMAX <= kMaxNt && NXM % kWave == 0, "slab class");
 
   const int sid = A.order[blockIdx.x];
   const snap_sample_desc D = A.descs[sid];
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           if constexpr (M != kStart) {
             g = (uu - uh) + a * lk + lm;
             Sg += g; Sug += uu * g;
-            st = fmax(st, fabs(g));
+            st = max_abs(st, g);
           }
           if (ic) {
             const double gi = M == kStart ? aux[xs + G * j] : sh.gic[xs + G * j];
@@ -437,6 +446,10 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     // ------------------------------------------------ wavefront 0: accept, test, solve
     if (w == 0) {
       int done = 0, acc = 0, bt = 0, soc = 0;
+      // per-wavefront partials of the last pass, lane q holding wavefront q's
+      const int qi = lane < NW ? lane : 0;
+      const bool qv = lane < NW;
+      const double qst = sh.red[qi][0], qpp = sh.red[qi][1], qdd = sh.red[qi][2];
       // rows k = lane and lane + 64 (nr <= 127): h from the slab sums, once
       double hk[2];
 #pragma unroll
@@ -450,13 +463,12 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       if (pend) {
         // penalty mu >= 1.1 ||lam+||_inf of the pending step (IC rows' part
         // from the trial pass)
-        mu = fmax(mu, 1.1 * fmax(lmrow, sh.scal[5]) + 1e-8);
+        mu = bcast_first(fmax(mu, 1.1 * fmax(lmrow, sh.scal[5]) + 1e-8));
         // Armijo test of phi = 1/2||u - u_hat||^2 + mu||h||_1 at alpha = 1; the
         // change is formed from differences, d.p + p.p/2 + mu(||h_t||_1 - ||h||_1),
         // so rounding of the large sums in phi never decides.  Local phase
         // (||h||_inf <= 1e-6): full Newton steps.
-        double pp = 0.0, dd = 0.0;
-        for (int q = 0; q < NW; ++q) { pp += sh.red[q][1]; dd += sh.red[q][2]; }
+        const double pp = wave_sum(qv ? qpp : 0.0), dd = wave_sum(qv ? qdd : 0.0);
         const double dphi = dd - mu * h1cur;
         const double dphit = dd + 0.5 * pp + mu * (h1 - h1cur);
         acc = (dphit <= 1e-4 * dphi) || !(dphi < 0.0) || hinf <= 1e-6;
@@ -464,10 +476,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         // increased the constraint violation (the curvature of h is what failed)
         soc = SOC && !acc && h1 > h1cur;
         if (acc) {
-#pragma unroll
-          for (int r = 0; r < RMAX; ++r)
-#pragma unroll
-            for (int j = 0; j < XPL; ++j) u[r][j] += 1.0 * pst[r][j];
+          // (u += p is applied by every wavefront after the barrier)
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int k = lane + kWave * e;
@@ -479,7 +488,8 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
               sh.rW[k] = rcp_nr(wk);
             }
           }
-          for (int x = lane; x < nx; x += kWave) sh.lamic[x] = sh.lampic[x];
+#pragma unroll
+          for (int e = 0; e < NXM / kWave; ++e) sh.lamic[lane + kWave * e] = sh.lampic[lane + kWave * e];
           wave_sync();
         } else {
           bt = 1;
@@ -504,10 +514,9 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         }
         hmax = wave_max(hmax);
         nf = __any(nf);
-        double stmax = 0.0;
-        for (int q = 0; q < NW; ++q) stmax = fmax(stmax, sh.red[q][0]);
+        const double stmax = wave_max(qv ? qst : 0.0);
         if (!bwd) {
-          hinf = hmax; stinf = stmax; h1cur = h1;
+          hinf = bcast_first(hmax); stinf = bcast_first(stmax); h1cur = bcast_first(h1);
           if (nf || !finite(hmax) || !finite(stmax)) done = 2;
           else if (hmax <= A.opt.tol_h && stmax <= A.opt.tol_s * uscale) done = 1;
           else if (it >= max_it) done = 3;
@@ -560,7 +569,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
               lm = fmax(lm, fabs(l));
             }
           }
-          lmrow = wave_max(lm);
+          lmrow = bcast_first(wave_max(lm));
         }
       }
       if (lane == 0) { sh.flag[0] = done; sh.flag[1] = acc; sh.flag[2] = bt | (soc << 1); }
@@ -568,12 +577,10 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     lds_barrier();
     const int done = sh.flag[0], acc = sh.flag[1], bt = sh.flag[2] & 1, soc_try = sh.flag[2] >> 1;
     if (acc) {
-      if (w != 0) {
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r)
+      for (int r = 0; r < RMAX; ++r)
 #pragma unroll
-          for (int j = 0; j < XPL; ++j) u[r][j] += 1.0 * pst[r][j];
-      }
+        for (int j = 0; j < XPL; ++j) u[r][j] += 1.0 * pst[r][j];
       ++iters;
     }
     if (bt) {
