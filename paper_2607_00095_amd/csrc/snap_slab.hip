@@ -23,8 +23,9 @@
 // entry and right-hand side.
 //
 // Layout.  One workgroup owns one sample for the whole Newton loop.  G
-// consecutive lanes form a group that owns one time slab per round
-// (slab = group + groups*round), lane `sub` of the group owns
+// consecutive lanes form a group that owns one time slab per round (round r
+// covers slabs groups*r .. groups*(r+1)-1, the wavefronts' blocks of them
+// rotated by one per round), lane `sub` of the group owns
 // x = sub, sub+G, ...; the field u and the step p stay in registers and u_hat
 // in LDS.  A slab sum is a log2(G)-step DPP scan inside the group, so every
 // slab of a wavefront reduces at once.
@@ -208,7 +209,8 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   constexpr int NG = NT / G;       // slab groups per round
   constexpr int GPW = kWave / G;   // groups per wavefront
   constexpr int NXM = G * XPL;     // widest grid of the class
-  static_assert(NW <= 16 && G <= kWave && NG * RMAX <= kMaxNt && NXM % kWave == 0, "slab class");
+  static_assert(NW <= 16 && (NW & (NW - 1)) == 0 && G <= kWave && NG * RMAX <= kMaxNt &&
+                NXM % kWave == 0, "slab class");
 
   const int sid = A.order[blockIdx.x];
   const snap_sample_desc D = A.descs[sid];
@@ -232,22 +234,25 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   const double* aux = A.aux + D.aux_off;
   const double m0 = f2 ? 0.0 : aux[nx];
 
-  auto slab = [&](int r) { return grp + NG * r; };
+  // Group g takes slab ((g + r*GPW) mod NG) + NG*r in round r: round 0 is
+  // slab g (slab 0, with the IC rows, on wavefront 0), and each later round
+  // moves the wavefronts' blocks of slabs by one, so a partial last round
+  // lands on another wavefront than the one that carries the IC rows.
+  auto slab_of = [&](int g, int r) { return ((g + r * GPW) & (NG - 1)) + NG * r; };
+  auto slab = [&](int r) { return slab_of(grp, r); };
   auto xat = [&](int j) { return sub + G * j; };
-  // element (round r, j) sits at k*nx + x = base + r*rstride + G*j
-  const int base = grp * nx + sub;
-  const int rstride = __builtin_amdgcn_readfirstlane(NG * nx);
-  auto eidx_from = [&](int b, int r, int j) { return b + r * rstride + G * j; };
-  auto eidx = [&](int r, int j) { return eidx_from(base, r, j); };
+  // element (round r, j) sits at k*nx + x
+  auto eidx = [&](int r, int j) { return slab(r) * nx + sub + G * j; };
   // The Newton loop re-reads u_hat and the IC targets from LDS in every pass;
-  // an opaque copy of the lane's base index keeps the compiler from hoisting
+  // an opaque copy of the lane's indices keeps the compiler from hoisting
   // those loop-invariant reads into registers (which would not fit).
   auto opaque = [](int v) {
     asm volatile("" : "+v"(v));
     return v;
   };
-  // wavefront w holds a slab < nt in round r (uniform over the wavefront)
-  auto live = [&](int r) { return w * GPW + NG * r < nt; };
+  // wavefront w holds a slab < nt in round r (uniform over the wavefront):
+  // its groups take the block of slabs starting at ((w + r) mod NW)*GPW + NG*r
+  auto live = [&](int r) { return ((w + r) & (NW - 1)) * GPW + NG * r < nt; };
   auto coef = [&](int k, double uu) { return k < nr ? a0c + a1c * uu : 0.0; };
   auto wslab = [&](int k, double l) { return k < nr ? fmax(1.0 + 2.0 * c * l, kWFloor) : 1.0; };
 
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   auto sums_pass = [&](const double* lamv, const double* lamicv, auto kind) {
     constexpr int M = decltype(kind)::value;
     constexpr bool step = M == kStep;
-    const int eb = opaque(base), xs = opaque(sub), gq = opaque(grp);
+    const int xs = opaque(sub), gq = opaque(grp);
     double st = 0.0, pp = 0.0, dd = 0.0;
     // W_0 at the point the sums describe: of lam+ at a trial point, else the
     // stored one (the adjoint keeps W of lam* while its multipliers are zero)
@@ -323,7 +328,8 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
       if (!live(r)) continue;
-      const int k = gq + NG * r;
+      const int k = slab_of(gq, r);
+      const int eb = k * nx + xs;   // element (k, xs + G*j) at eb + G*j
       const bool kv = k < nt;
       const bool law = k < nr;
       // per-slab constants: a = a0 + a1 u on law slabs (0 on the last slab);
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         const int x = xat(j);
         if (kv && x < nx) {
           double uu = u[r][j];
-          const double uh = M == kStart ? uu : uhl[eb + r * rstride + G * j];
+          const double uh = M == kStart ? uu : uhl[eb + G * j];
           double lm = lkm;
           if (ic) {
             if constexpr (step) {
@@ -625,12 +631,13 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         lds_barrier();
         // trial u + q: slab sums for h, the IC rows, and the merit terms of q
         {
-          const int xs = opaque(sub), gq = opaque(grp), eb = opaque(base);
+          const int xs = opaque(sub), gq = opaque(grp);
           double qq = 0.0, dq = 0.0;
 #pragma unroll
           for (int r = 0; r < RMAX; ++r) {
             if (!live(r)) continue;
-            const int k = gq + NG * r;
+            const int k = slab_of(gq, r);
+            const int eb = k * nx + xs;
             const bool kv = k < nt;
             const double zk = (k < nr) ? sh.dx[k] : 0.0;
             const double zkm = (k >= 1 && kv) ? sh.dx[k - 1] : 0.0;
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
                 const double zm = (r == 0 && k == 0) ? sh.ric[xs + G * j] : zkm;
                 const double q = pst[r][j] - (coef(k, uu) * zk + zm) * rW;
                 const double us = uu + q;
-                const double d = uu - uhl[eb + r * rstride + G * j];
+                const double d = uu - uhl[eb + G * j];
                 qq += q * q;
                 dq += d * q;
                 Su += us; Suu += us * us;
@@ -676,7 +683,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           const int xs = opaque(sub), gq = opaque(grp);
 #pragma unroll
           for (int r = 0; r < RMAX; ++r) {
-            const int k = gq + NG * r;
+            const int k = slab_of(gq, r);
             const bool kv = k < nt;
             const double zk = (k < nr) ? sh.dx[k] : 0.0;
             const double zkm = (k >= 1 && kv) ? sh.dx[k - 1] : 0.0;
@@ -718,7 +725,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
           if (!live(r)) continue;
-          const int k = gq + NG * r;
+          const int k = slab_of(gq, r);
           double Su = 0, Suu = 0, h1 = 0;
 #pragma unroll
           for (int j = 0; j < XPL; ++j) {
@@ -779,11 +786,11 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     }
     if (bwd) {
       // the adjoint is the step of the linearized system: write it and stop
-      const int eb = opaque(base), gq = opaque(grp);
+      const int xs = opaque(sub), gq = opaque(grp);
 #pragma unroll
       for (int r = 0; r < RMAX; ++r) {
         if (!live(r)) continue;
-        const int k = gq + NG * r;
+        const int k = slab_of(gq, r);
         const double lk = (k < nr) ? sh.lamp[k] : 0.0;
         const double lkm = (k >= 1 && k < nt) ? sh.lamp[k - 1] : 0.0;
         const double rW = k < nt ? sh.rW[k] : 1.0;
@@ -794,7 +801,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
             const double uu = u[r][j];
             // IC rows: lam_ic = 0, so the increment is W_0 r_ic - a_0 dlam_0
             const double lic = (r == 0 && k == 0) ? sh.W[0] * sh.ric[x] - coef(0, uu) * sh.scal[4] : 0.0;
-            const int e = eidx_from(eb, r, j);
+            const int e = k * nx + xs + G * j;
             const double jt = (uu - uhl[e]) + coef(k, uu) * lk + lkm + lic;
             A.grad_uhat[vo + e] = -jt * rW;
           }
@@ -811,14 +818,14 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
 
   // ---------------------------------------------------------------- outputs
   if (!bwd) {
-    const int eb = opaque(base), gq = opaque(grp);
+    const int xs = opaque(sub), gq = opaque(grp);
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
-      const int k = gq + NG * r;
+      const int k = slab_of(gq, r);
 #pragma unroll
       for (int j = 0; j < XPL; ++j) {
         const int x = xat(j);
-        if (k < nt && x < nx) A.u[vo + eidx_from(eb, r, j)] = u[r][j];
+        if (k < nt && x < nx) A.u[vo + k * nx + xs + G * j] = u[r][j];
       }
     }
     for (int x = tid; x < nx; x += NT) A.lam[D.row_off + x] = sh.lamic[x];
