@@ -70,6 +70,10 @@ struct PcrBuf {
 // unknowns (each even equation takes its two odd neighbours), parallel cyclic
 // reduction solves the <= 64 even equations, one per lane, and the odd
 // unknowns follow by back-substitution.  One reciprocal per equation and level.
+// No lane branches: an equation's coupling to a neighbour that does not exist
+// is exactly zero (and lanes past the last even equation hold identity rows),
+// so every lane reads clamped, in-range neighbours and adds zero terms; all
+// reads of a level are issued together.
 template <typename TS>
 __device__ void pcr_solve(int n, const double* Td, const double* To, const double* rhs,
                           double* x, PcrBuf<TS>& B) {
@@ -88,19 +92,17 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   const TS r1 = rcp_nr(b1);
   B.oa[l] = a1; B.oc[l] = c1; B.od[l] = d1; B.orb[l] = r1;
   wave_sync();
-  // even equation 2l with odd neighbours 2l-1 (lane l-1) and 2l+1 (own)
-  TS A = 0, Bv = b0, C = 0, Dv = d0;
-  if (l > 0) {
-    const TS al = -a0 * B.orb[l - 1];
-    A = al * B.oa[l - 1];
-    Bv += al * B.oc[l - 1];
-    Dv += al * B.od[l - 1];
-  }
+  // even equation 2l with odd neighbours 2l-1 (lane l-1; a0 = 0 on lane 0)
+  // and 2l+1 (own)
+  TS A, Bv, C, Dv;
   {
-    const TS ga = -c0 * r1;
+    const int lm = l > 0 ? l - 1 : 0;
+    const TS orb = B.orb[lm], oa = B.oa[lm], oc = B.oc[lm], od = B.od[lm];
+    const TS al = -a0 * orb, ga = -c0 * r1;
+    A = al * oa;
     C = ga * c1;
-    Bv += ga * a1;
-    Dv += ga * d1;
+    Bv = b0 + al * oc + ga * a1;
+    Dv = d0 + al * od + ga * d1;
   }
   if (l >= m) { A = 0; Bv = 1; C = 0; Dv = 0; }
   TS rB = rcp_nr(Bv);
@@ -108,23 +110,18 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   for (int s = 1; s < m; s <<= 1) {
     B.a[cur][l] = A; B.c[cur][l] = C; B.d[cur][l] = Dv; B.rb[cur][l] = rB;
     wave_sync();
-    if (l < m) {
-      TS An = 0, Cn = 0;
-      if (l - s >= 0) {
-        const TS al = -A * B.rb[cur][l - s];
-        An = al * B.a[cur][l - s];
-        Bv += al * B.c[cur][l - s];
-        Dv += al * B.d[cur][l - s];
-      }
-      if (l + s < m) {
-        const TS ga = -C * B.rb[cur][l + s];
-        Cn = ga * B.c[cur][l + s];
-        Bv += ga * B.a[cur][l + s];
-        Dv += ga * B.d[cur][l + s];
-      }
-      A = An; C = Cn;
-      rB = rcp_nr(Bv);
-    }
+    // A = 0 when l - s < 0 and C = 0 when l + s >= m: those terms add zero
+    const int lo = l >= s ? l - s : l, hi = l + s < kWave ? l + s : l;
+    const TS rbm = B.rb[cur][lo], am = B.a[cur][lo], cm = B.c[cur][lo], dm = B.d[cur][lo];
+    const TS rbp = B.rb[cur][hi], ap = B.a[cur][hi], cp = B.c[cur][hi], dpv = B.d[cur][hi];
+    const TS al = -A * rbm, ga = -C * rbp;
+    A = al * am;
+    C = ga * cp;
+    Bv += al * cm;
+    Bv += ga * ap;
+    Dv += al * dm;
+    Dv += ga * dpv;
+    rB = rcp_nr(Bv);
     cur ^= 1;
   }
   const double xe = (double)(Dv * rB);
@@ -482,17 +479,19 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         // increased the constraint violation (the curvature of h is what failed)
         soc = SOC && !acc && h1 > h1cur;
         if (acc) {
-          // (u += p is applied by every wavefront after the barrier)
+          // (u += p is applied by every wavefront after the barrier).  Rows
+          // past nr hold lam+ = 0 and W = 1 throughout, so all 128 entries
+          // are rewritten without a branch.
+          static_assert(kMaxNt == 2 * kWave, "two rows per lane");
+          const double lp0 = sh.lamp[lane], lp1 = sh.lamp[lane + kWave];
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int k = lane + kWave * e;
-            if (k < nr) {
-              const double l = sh.lamp[k];
-              const double wk = wslab(k, l);
-              sh.lam[k] = l;
-              sh.W[k] = wk;
-              sh.rW[k] = rcp_nr(wk);
-            }
+            const double l = e ? lp1 : lp0;
+            const double wk = wslab(k, l);
+            sh.lam[k] = l;
+            sh.W[k] = wk;
+            sh.rW[k] = rcp_nr(wk);
           }
 #pragma unroll
           for (int e = 0; e < NXM / kWave; ++e) sh.lamic[lane + kWave * e] = sh.lampic[lane + kWave * e];
@@ -504,19 +503,29 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       if (!bt) {
         double hmax = (lane == 0) ? sh.scal[1] : 0.0;
         bool nf = false;
+        // rows k = lane, lane + 64: every read issued up front (index k + 1
+        // clamped into the arrays); entries past nr - 1 are written too and
+        // never read (the solve reads rows < nr only)
+        const double sar0 = sh.scal[0];
+        double rWk[2], rWk1[2], sad[2], sdn[2], sa2[2], san[2];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int k = lane + kWave * e;
-          if (k < nr) {
-            const double rWk = sh.rW[k], rWk1 = sh.rW[k + 1];
-            double rk = hk[e] - (sh.Sad[k] * rWk + sh.Sd[k + 1] * rWk1);
-            if (k == 0) rk -= sh.scal[0];
-            sh.r[k] = rk;
-            sh.Td[k] = (k == 0 ? 0.0 : sh.Sa2[k] * rWk) + (double)nx * rWk1;
-            sh.To[k] = (k + 1 < nr) ? sh.Sa[k + 1] * rWk1 : 0.0;
-            hmax = fmax(hmax, fabs(hk[e]));
-            nf |= !finite(hk[e]);
-          }
+          const int k1 = k + 1 < kMaxNt ? k + 1 : k;
+          rWk[e] = sh.rW[k]; rWk1[e] = sh.rW[k1];
+          sad[e] = sh.Sad[k]; sdn[e] = sh.Sd[k1];
+          sa2[e] = sh.Sa2[k]; san[e] = sh.Sa[k1];
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int k = lane + kWave * e;
+          double rk = hk[e] - (sad[e] * rWk[e] + sdn[e] * rWk1[e]);
+          if (k == 0) rk -= sar0;
+          sh.r[k] = rk;
+          sh.Td[k] = (k == 0 ? 0.0 : sa2[e] * rWk[e]) + (double)nx * rWk1[e];
+          sh.To[k] = (k + 1 < nr) ? san[e] * rWk1[e] : 0.0;
+          hmax = fmax(hmax, fabs(hk[e]));   // hk = 0 past nr - 1
+          nf |= !finite(hk[e]);
         }
         hmax = wave_max(hmax);
         nf = __any(nf);
