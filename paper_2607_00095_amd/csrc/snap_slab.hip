@@ -81,14 +81,18 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   const int j0 = 2 * l, j1 = 2 * l + 1;
   const int m = (n + 1) / 2;   // even equations
   const bool v0 = j0 < n, v1 = j1 < n;
-  const TS a0 = (v0 && j0 > 0) ? (TS)To[j0 - 1] : (TS)0;
-  const TS b0 = v0 ? (TS)Td[j0] : (TS)1;
-  const TS c0 = (v0 && j0 + 1 < n) ? (TS)To[j0] : (TS)0;
-  const TS d0 = v0 ? (TS)rhs[j0] : (TS)0;
-  const TS a1 = v1 ? (TS)To[j1 - 1] : (TS)0;
-  const TS b1 = v1 ? (TS)Td[j1] : (TS)1;
-  const TS c1 = (v1 && j1 + 1 < n) ? (TS)To[j1] : (TS)0;
-  const TS d1 = v1 ? (TS)rhs[j1] : (TS)0;
+  // rows 2l, 2l+1 < 128 lie inside the arrays: read unconditionally, then
+  // keep only the rows of the system (rows past n - 1 become identity rows)
+  const double tom = To[j0 > 0 ? j0 - 1 : 0], td0 = Td[j0], to0 = To[j0], rh0 = rhs[j0];
+  const double td1 = Td[j1], to1 = To[j1], rh1 = rhs[j1];
+  const TS a0 = (v0 && j0 > 0) ? (TS)tom : (TS)0;
+  const TS b0 = v0 ? (TS)td0 : (TS)1;
+  const TS c0 = (v0 && j0 + 1 < n) ? (TS)to0 : (TS)0;
+  const TS d0 = v0 ? (TS)rh0 : (TS)0;
+  const TS a1 = v1 ? (TS)to0 : (TS)0;
+  const TS b1 = v1 ? (TS)td1 : (TS)1;
+  const TS c1 = (v1 && j1 + 1 < n) ? (TS)to1 : (TS)0;
+  const TS d1 = v1 ? (TS)rh1 : (TS)0;
   const TS r1 = rcp_nr(b1);
   B.oa[l] = a1; B.oc[l] = c1; B.od[l] = d1; B.orb[l] = r1;
   wave_sync();
@@ -458,7 +462,11 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int k = lane + kWave * e;
-        hk[e] = (k < nr && !bwd) ? row_h(k) : 0.0;
+        // reads unconditional (k + 1 clamped into the array), value kept for rows < nr
+        const int k1 = k + 1 < kMaxNt ? k + 1 : k;
+        const double s1k = sh.S1[k], s1n = sh.S1[k1], s2k = sh.S2[k];
+        const double h = f2 ? s1n - s1k - c * s2k : s1n - m0;
+        hk[e] = (k < nr && !bwd) ? h : 0.0;
       }
       double h1 = (lane == 0) ? sh.scal[2] : 0.0;
       h1 += fabs(hk[0]) + fabs(hk[1]);
@@ -542,17 +550,30 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           if constexpr (sizeof(TS) != sizeof(double)) {
             // float32 solve, float64 residual and refinement
             constexpr int max_ref = 4;
+            // rows k = lane, lane + 64; reads unconditional with clamped
+            // neighbours, values kept for rows < nr
             double rn = 0.0;
-            for (int k = lane; k < nr; k += kWave) rn = fmax(rn, fabs(sh.r[k]));
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              const int k = lane + kWave * e;
+              const double rk = sh.r[k];
+              rn = fmax(rn, k < nr ? fabs(rk) : 0.0);
+            }
             rn = wave_max(rn);
             for (int ref = 0; ref < max_ref; ++ref) {
               double resmax = 0.0;
-              for (int k = lane; k < nr; k += kWave) {
-                double tx = sh.Td[k] * sh.lamp[k];
-                if (k > 0) tx += sh.To[k - 1] * sh.lamp[k - 1];
-                if (k + 1 < nr) tx += sh.To[k] * sh.lamp[k + 1];
-                sh.res[k] = sh.r[k] - tx;
-                resmax = fmax(resmax, fabs(sh.res[k]));
+#pragma unroll
+              for (int e = 0; e < 2; ++e) {
+                const int k = lane + kWave * e;
+                const int km = k > 0 ? k - 1 : 0, kp = k + 1 < kMaxNt ? k + 1 : k;
+                const double tdk = sh.Td[k], lk = sh.lamp[k], tom = sh.To[km], lkm = sh.lamp[km];
+                const double tok = sh.To[k], lkp = sh.lamp[kp], rk = sh.r[k];
+                double tx = tdk * lk;
+                tx += k > 0 ? tom * lkm : 0.0;
+                tx += k + 1 < nr ? tok * lkp : 0.0;
+                const double res = rk - tx;
+                if (k < nr) sh.res[k] = res;
+                resmax = fmax(resmax, k < nr ? fabs(res) : 0.0);
               }
               resmax = wave_max(resmax);
               wave_sync();
@@ -563,7 +584,12 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
                                         : (hinf > 1e-6 ? 1e-6 * rn : fmax(1e-15 * rn, 0.1 * A.opt.tol_h));
               if (!(resmax > target)) break;
               pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
-              for (int k = lane; k < nr; k += kWave) sh.lamp[k] += sh.dx[k];
+#pragma unroll
+              for (int e = 0; e < 2; ++e) {
+                const int k = lane + kWave * e;
+                const double lk = sh.lamp[k], dxk = sh.dx[k];
+                if (k < nr) sh.lamp[k] = lk + dxk;
+              }
               wave_sync();
               ++refines;
             }
@@ -578,11 +604,10 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int k = lane + kWave * e;
-            if (k < nr) {
-              const double l = sh.lamp[k] + sh.lam[k];
-              sh.lamp[k] = l;
-              lm = fmax(lm, fabs(l));
-            }
+            // rows past nr - 1 hold zeros in both (no branch needed)
+            const double l = sh.lamp[k] + sh.lam[k];
+            sh.lamp[k] = l;
+            lm = fmax(lm, fabs(l));
           }
           lmrow = bcast_first(wave_max(lm));
         }
