@@ -322,7 +322,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     constexpr int M = decltype(kind)::value;
     constexpr bool step = M == kStep;
     const int xs = opaque(sub), gq = opaque(grp);
-    double st = 0.0, pp = 0.0, dd = 0.0;
+    double st = 0.0, pp = -0.0, dd = -0.0;
     // W_0 at the point the sums describe: of lam+ at a trial point, else the
     // stored one (the adjoint keeps W of lam* while its multipliers are zero)
     const double rW0 = step ? rcp_nr(wslab(0, nr > 0 ? lamv[0] : 0.0)) : (M == kStart ? 1.0 : sh.rW[0]);
@@ -343,15 +343,21 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       const double rWc = (kv && step) ? sh.rW[k] : 1.0;
       const double W0 = (ic && step) ? sh.W[0] : 0.0;
       const double dl0 = (ic && step) ? sh.scal[4] : 0.0;
-      double Su = 0, Suu = 0, Sg = 0, Sug = 0, sar = 0, hmx = 0, h1 = 0, lpm = 0;
+      // With the multipliers fixed, g is affine in u on a slab:
+      // g = (u - u_hat) + gam u + bet, gam = a1 lk, bet = a0 lk + (the +1
+      // coefficient's multiplier: row k-1's, or the IC row's on slab 0).
+      // The accumulators start at -0, which the first add folds away.
+      const double gam = a1 * lk, bet = a0 * lk + lkm;
+      double Su = -0.0, Suu = -0.0, Sg = -0.0, Sug = -0.0, sar = -0.0, hmx = 0, h1 = -0.0, lpm = 0;
 #pragma unroll
       for (int j = 0; j < XPL; ++j) {
         const int x = xat(j);
         if (kv && x < nx) {
           double uu = u[r][j];
           const double uh = M == kStart ? uu : uhl[eb + G * j];
-          double lm = lkm;
+          double bx = bet;
           if (ic) {
+            double lm;
             if constexpr (step) {
               lm = sh.lamic[xs + G * j] + (W0 * sh.ric[xs + G * j] - (a0 + a1 * uu) * dl0);
               sh.lampic[xs + G * j] = lm;
@@ -359,25 +365,28 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
             } else {
               lm = M == kStart ? 0.0 : lamicv[xs + G * j];
             }
+            bx = a0 * lk + lm;
           }
           if constexpr (step) {
             const double d = uu - uh;
-            const double jt = d + (a0 + a1 * uu) * lk + lm;
+            const double jt = fma(uu, gam, d) + bx;
             const double p = -jt * rWc;
             pst[r][j] = p;
-            pp += p * p;
-            dd += d * p;
+            pp = fma(p, p, pp);
+            dd = fma(d, p, dd);
             uu = uu + 1.0 * p;
           }
-          const double a = a0 + a1 * uu;
-          Su += uu; Suu += uu * uu;
+          Su += uu;
+          Suu = fma(uu, uu, Suu);
           double g = 0.0;
           if constexpr (M != kStart) {
-            g = (uu - uh) + a * lk + lm;
-            Sg += g; Sug += uu * g;
+            g = fma(uu, gam, uu - uh) + bx;
+            Sg += g;
+            Sug = fma(uu, g, Sug);
             st = max_abs(st, g);
           }
           if (ic) {
+            const double a = a0 + a1 * uu;
             const double gi = M == kStart ? aux[xs + G * j] : sh.gic[xs + G * j];
             const double hic = bwd ? 0.0 : uu - gi;
             const double ric = hic - g * rW0;
