@@ -165,6 +165,25 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// Row totals (16 lanes) of four values at once.  Two exchange steps
+// (partner lane ^ 1, then lane ^ 2) leave every lane with a four-lane
+// partial of one value, index ((lane & 1) << 1) | ((lane >> 1) & 1), and two
+// rotations of the row by 4 and 8 lanes add its four quads, so every lane
+// ends with the row total of its value.
+__device__ __forceinline__ double row_sum4(double v0, double v1, double v2, double v3, int lane) {
+  const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0;
+  double ka = b0 ? v2 : v0, kb = b0 ? v3 : v1;
+  const double sa = b0 ? v0 : v2, sb = b0 ? v1 : v3;
+  ka += dpp_d<0xB1, 0xf, false>(sa);   // quad_perm [1,0,3,2]
+  kb += dpp_d<0xB1, 0xf, false>(sb);
+  double k = b1 ? kb : ka;
+  const double sk = b1 ? ka : kb;
+  k += dpp_d<0x4E, 0xf, false>(sk);    // quad_perm [2,3,0,1]
+  k += dpp_d<0x124, 0xf, false>(k);    // row_ror:4
+  k += dpp_d<0x128, 0xf, false>(k);    // row_ror:8
+  return k;
+}
+
 // group maximum of non-negative values (same scan, fmax)
 template <int G>
 __device__ __forceinline__ double group_max(double v) {
@@ -179,9 +198,10 @@ __device__ __forceinline__ double group_max(double v) {
 
 template <int NXM>
 struct SlabSh {
-  // per-slab sums at the current (or trial) point: S1 = sum u, S2 = sum u(1-u),
-  // Sd = sum g, and the Schur quantities Sa = sum a, Sa2 = sum a^2, Sad = sum a g
-  double S1[kMaxNt], S2[kMaxNt], Sd[kMaxNt], Sa[kMaxNt], Sa2[kMaxNt], Sad[kMaxNt];
+  // per-slab sums at the current (or trial) point: Sr[0] = sum u,
+  // Sr[1] = sum u^2, Sr[2] = sum g, Sr[3] = sum u g (the Schur quantities
+  // sum a, sum a^2, sum a g follow from them, a being affine in u)
+  double Sr[4][kMaxNt];
   double W[kMaxNt];      // W_k per slab at the current point
   double rW[kMaxNt];     // 1/W_k
   double lam[kMaxNt];    // multipliers of the slab rows at the current point
@@ -397,14 +417,15 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           }
         }
       }
-      Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
-      if constexpr (M != kStart) { Sg = group_sum<G>(Sg); Sug = group_sum<G>(Sug); }
-      if (glast && kv) {
-        const double cnt = (double)nx;
-        sh.S1[k] = Su; sh.S2[k] = Su - Suu; sh.Sd[k] = Sg;
-        sh.Sa[k] = a0 * cnt + a1 * Su;
-        sh.Sa2[k] = a0 * a0 * cnt + 2.0 * a0 * a1 * Su + a1 * a1 * Suu;
-        sh.Sad[k] = a0 * Sg + a1 * Sug;
+      if constexpr (M != kStart && G == 16) {
+        // a group is a row: one transposed reduction, four lanes write
+        const double t = row_sum4(Su, Suu, Sg, Sug, lane);
+        const int vi = ((lane & 1) << 1) | ((lane >> 1) & 1);
+        if ((lane & 12) == 0 && kv) sh.Sr[vi][k] = t;
+      } else {
+        Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
+        if constexpr (M != kStart) { Sg = group_sum<G>(Sg); Sug = group_sum<G>(Sug); }
+        if (glast && kv) { sh.Sr[0][k] = Su; sh.Sr[1][k] = Suu; sh.Sr[2][k] = Sg; sh.Sr[3][k] = Sug; }
       }
       if (w == 0 && r == 0) {   // group 0 holds slab 0 and the IC rows
         sar = group_sum<G>(sar); h1 = group_sum<G>(h1); hmx = group_max<G>(hmx);
@@ -437,7 +458,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
 
   // feasibility row k from the slab sums S1, S2
   auto row_h = [&](int k) -> double {
-    return f2 ? sh.S1[k + 1] - sh.S1[k] - c * sh.S2[k] : sh.S1[k + 1] - m0;
+    return f2 ? sh.Sr[0][k + 1] - sh.Sr[0][k] - c * (sh.Sr[0][k] - sh.Sr[1][k]) : sh.Sr[0][k + 1] - m0;
   };
   // sum of |h| over all rows (IC rows from scal[2]); wavefront 0 only
   auto h1_rows = [&]() -> double {
@@ -473,7 +494,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         const int k = lane + kWave * e;
         // reads unconditional (k + 1 clamped into the array), value kept for rows < nr
         const int k1 = k + 1 < kMaxNt ? k + 1 : k;
-        const double s1k = sh.S1[k], s1n = sh.S1[k1], s2k = sh.S2[k];
+        const double s1k = sh.Sr[0][k], s1n = sh.Sr[0][k1], s2k = s1k - sh.Sr[1][k];
         const double h = f2 ? s1n - s1k - c * s2k : s1n - m0;
         hk[e] = (k < nr && !bwd) ? h : 0.0;
       }
@@ -525,13 +546,25 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         // never read (the solve reads rows < nr only)
         const double sar0 = sh.scal[0];
         double rWk[2], rWk1[2], sad[2], sdn[2], sa2[2], san[2];
+        // an opaque row index: these reads are issued again here rather than
+        // kept live in registers from the test above
+        const int lo = opaque(lane);
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-          const int k = lane + kWave * e;
+          const int k = lo + kWave * e;
           const int k1 = k + 1 < kMaxNt ? k + 1 : k;
           rWk[e] = sh.rW[k]; rWk1[e] = sh.rW[k1];
-          sad[e] = sh.Sad[k]; sdn[e] = sh.Sd[k1];
-          sa2[e] = sh.Sa2[k]; san[e] = sh.Sa[k1];
+          // sum a g, sum a^2 on slab k and sum a on slab k + 1 from the raw sums
+          // (a = a0 + a1 u on slabs < nr, 0 on the last)
+          const double su = sh.Sr[0][k], suu = sh.Sr[1][k], sg = sh.Sr[2][k], sug = sh.Sr[3][k];
+          const double su1 = sh.Sr[0][k1], sg1 = sh.Sr[2][k1];
+          const double ak0 = k < nr ? a0c : 0.0, ak1 = k < nr ? a1c : 0.0;
+          const double an0 = k1 < nr ? a0c : 0.0, an1 = k1 < nr ? a1c : 0.0;
+          const double cnt = (double)nx;
+          sad[e] = ak0 * sg + ak1 * sug;
+          sdn[e] = sg1;
+          sa2[e] = ak0 * ak0 * cnt + 2.0 * ak0 * ak1 * su + ak1 * ak1 * suu;
+          san[e] = an0 * cnt + an1 * su1;
         }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -702,7 +735,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
               }
             }
             Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
-            if (glast && kv) { sh.S1[k] = Su; sh.S2[k] = Su - Suu; }
+            if (glast && kv) { sh.Sr[0][k] = Su; sh.Sr[1][k] = Suu; }
             if (w == 0 && r == 0) {
               h1 = group_sum<G>(h1);
               if (lane == G - 1) sh.scal[2] = h1;
@@ -780,7 +813,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
             }
           }
           Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
-          if (glast && k < nt) { sh.S1[k] = Su; sh.S2[k] = Su - Suu; }
+          if (glast && k < nt) { sh.Sr[0][k] = Su; sh.Sr[1][k] = Suu; }
           if (w == 0 && r == 0) {
             h1 = group_sum<G>(h1);
             if (lane == G - 1) sh.scal[2] = h1;
