@@ -50,7 +50,7 @@ constexpr int kMaxNt = 128;
 constexpr double kWFloor = 0.1;
 
 // kinds of slab-sum pass (see the kernel)
-constexpr int kPoint = 0, kStep = 1, kStart = 2;
+constexpr int kPoint = 0, kStep = 1;
 template <int K>
 struct PassKind {
   static constexpr int value = K;
@@ -284,6 +284,8 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   bool nonfinite = false;
   // every load is issued before the first use (indices clamped, no branches);
   // the adjoint reads u* into u and grad_u into pst
+  // the forward's IC targets of slab 0 (wavefront 0) load with the field
+  double gi0[XPL];
   {
     const double* src = bwd ? A.u + vo : A.uhat + vo;
 #pragma unroll
@@ -295,7 +297,47 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         u[r][j] = src[idx];
         pst[r][j] = bwd ? A.grad_u[vo + idx] : 0.0;
       }
+#pragma unroll
+    for (int j = 0; j < XPL; ++j) gi0[j] = (!bwd && w == 0) ? aux[xat(j) < nx ? xat(j) : 0] : 0.0;
   }
+  // Forward start u = u_hat, lam = 0: g = 0 exactly, so a slab's sums are
+  // sum u and sum u^2 of the registers just loaded (slots outside the grid
+  // hold 0), formed round by round while later rounds' loads are in flight;
+  // on slab 0 the IC rows' h_ic, which is also r_ic here.
+  auto start_round = [&](int r) {
+    const int k = slab(r);
+    const bool kv = k < nt;
+    double Su = -0.0, Suu = -0.0;
+#pragma unroll
+    for (int j = 0; j < XPL; ++j) {
+      Su += u[r][j];
+      Suu = fma(u[r][j], u[r][j], Suu);
+    }
+    if constexpr (G == 16) {
+      const double t = row_sum4(Su, Suu, 0.0, 0.0, lane);
+      const int vi = ((lane & 1) << 1) | ((lane >> 1) & 1);
+      if ((lane & 12) == 0 && kv) sh.Sr[vi][k] = t;
+    } else {
+      Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
+      if (glast && kv) { sh.Sr[0][k] = Su; sh.Sr[1][k] = Suu; sh.Sr[2][k] = 0.0; sh.Sr[3][k] = 0.0; }
+    }
+    if (r == 0 && w == 0) {
+      const double a0 = nr > 0 ? a0c : 0.0, a1 = nr > 0 ? a1c : 0.0;
+      double sar = -0.0, hmx = 0.0, h1 = -0.0;
+#pragma unroll
+      for (int j = 0; j < XPL; ++j) {
+        const bool okx = grp == 0 && xat(j) < nx;
+        const double uu = u[0][j];
+        const double hic = uu - gi0[j];
+        if (okx) sh.ric[xat(j)] = hic;
+        sar += okx ? (a0 + a1 * uu) * hic : 0.0;
+        hmx = fmax(hmx, okx ? fabs(hic) : 0.0);
+        h1 += okx ? fabs(hic) : 0.0;
+      }
+      sar = group_sum<G>(sar); h1 = group_sum<G>(h1); hmx = group_max<G>(hmx);
+      if (lane == G - 1) { sh.scal[0] = sar; sh.scal[1] = hmx; sh.scal[2] = h1; }
+    }
+  };
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
     const int k = slab(r);
@@ -310,7 +352,10 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       umax = fmax(umax, fabs(hh));
       nonfinite |= !finite(hh) || !finite(uu);
     }
+    if (!bwd && live(r)) start_round(r);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (!bwd && lane == 0) { sh.red[w][0] = 0.0; sh.red[w][1] = 0.0; sh.red[w][2] = 0.0; }
   for (int x = tid; x < nx; x += NT) {
     sh.gic[x] = aux[x];
     sh.lamic[x] = 0.0;
@@ -326,7 +371,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     sh.lam[k] = 0.0;
     sh.lamp[k] = 0.0;
   }
-  // Slab sums at a point, in one of three forms (the pass kind is a
+  // Slab sums at a point, in one of two forms (the pass kind is a
   // compile-time constant, so each call site gets its own code):
   //   kPoint  the point u with multipliers lamv (slab rows), lamicv (IC rows);
   //   kStep   first the step p at the current point with lam+ (into pst),
@@ -334,8 +379,6 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   //           point u + p; the IC rows' lam+ is formed here, by the lanes that
   //           own slab 0 (lam+_ic = lam_ic + W_0 r_ic - a_0 dlam_0, stored
   //           for the line search and its maximum kept for the penalty);
-  //   kStart  the forward start u = u_hat, lam = 0, where g = 0 exactly, so
-  //           only sum u and sum u^2 are formed and nothing is read from LDS.
   // Per slab: sum u, sum u^2, sum g, sum u g, and the IC rows'
   // r_ic = h_ic - g/W_0 (W_0 of the multipliers the sums describe).
   auto sums_pass = [&](const double* lamv, const double* lamicv, auto kind) {
@@ -345,7 +388,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     double st = 0.0, pp = -0.0, dd = -0.0;
     // W_0 at the point the sums describe: of lam+ at a trial point, else the
     // stored one (the adjoint keeps W of lam* while its multipliers are zero)
-    const double rW0 = step ? rcp_nr(wslab(0, nr > 0 ? lamv[0] : 0.0)) : (M == kStart ? 1.0 : sh.rW[0]);
+    const double rW0 = step ? rcp_nr(wslab(0, nr > 0 ? lamv[0] : 0.0)) : sh.rW[0];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
       if (!live(r)) continue;
@@ -356,8 +399,8 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       // per-slab constants: a = a0 + a1 u on law slabs (0 on the last slab);
       // the +1 coefficient of row k-1 on slab k, or the IC multiplier on slab 0
       const double a0 = law ? a0c : 0.0, a1 = law ? a1c : 0.0;
-      const double lk = (law && M != kStart) ? lamv[k] : 0.0;
-      const double lkm = (k >= 1 && kv && M != kStart) ? lamv[k - 1] : 0.0;
+      const double lk = law ? lamv[k] : 0.0;
+      const double lkm = (k >= 1 && kv) ? lamv[k - 1] : 0.0;
       const bool ic = r == 0 && k == 0;
       // step at the current point: W of the current multipliers
       const double rWc = (kv && step) ? sh.rW[k] : 1.0;
@@ -374,7 +417,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         const int x = xat(j);
         if (kv && x < nx) {
           double uu = u[r][j];
-          const double uh = M == kStart ? uu : uhl[eb + G * j];
+          const double uh = uhl[eb + G * j];
           double bx = bet;
           if (ic) {
             double lm;
@@ -383,7 +426,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
               sh.lampic[xs + G * j] = lm;
               lpm = fmax(lpm, fabs(lm));
             } else {
-              lm = M == kStart ? 0.0 : lamicv[xs + G * j];
+              lm = lamicv[xs + G * j];
             }
             bx = a0 * lk + lm;
           }
@@ -398,16 +441,13 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           }
           Su += uu;
           Suu = fma(uu, uu, Suu);
-          double g = 0.0;
-          if constexpr (M != kStart) {
-            g = fma(uu, gam, uu - uh) + bx;
-            Sg += g;
-            Sug = fma(uu, g, Sug);
-            st = max_abs(st, g);
-          }
+          const double g = fma(uu, gam, uu - uh) + bx;
+          Sg += g;
+          Sug = fma(uu, g, Sug);
+          st = max_abs(st, g);
           if (ic) {
             const double a = a0 + a1 * uu;
-            const double gi = M == kStart ? aux[xs + G * j] : sh.gic[xs + G * j];
+            const double gi = sh.gic[xs + G * j];
             const double hic = bwd ? 0.0 : uu - gi;
             const double ric = hic - g * rW0;
             sh.ric[xs + G * j] = ric;
@@ -417,14 +457,14 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           }
         }
       }
-      if constexpr (M != kStart && G == 16) {
+      if constexpr (G == 16) {
         // a group is a row: one transposed reduction, four lanes write
         const double t = row_sum4(Su, Suu, Sg, Sug, lane);
         const int vi = ((lane & 1) << 1) | ((lane >> 1) & 1);
         if ((lane & 12) == 0 && kv) sh.Sr[vi][k] = t;
       } else {
         Su = group_sum<G>(Su); Suu = group_sum<G>(Suu);
-        if constexpr (M != kStart) { Sg = group_sum<G>(Sg); Sug = group_sum<G>(Sug); }
+        Sg = group_sum<G>(Sg); Sug = group_sum<G>(Sug);
         if (glast && kv) { sh.Sr[0][k] = Su; sh.Sr[1][k] = Suu; sh.Sr[2][k] = Sg; sh.Sr[3][k] = Sug; }
       }
       if (w == 0 && r == 0) {   // group 0 holds slab 0 and the IC rows
@@ -443,9 +483,6 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
     if (lane == 0) { sh.red[w][0] = st; sh.red[w][1] = pp; sh.red[w][2] = dd; }
   };
 
-  // the forward's first sums come from the registers just loaded, before the
-  // first barrier (they touch no LDS that the set-up above writes)
-  if (!bwd) sums_pass(sh.lam, sh.lamic, PassKind<kStart>{});
   {
     const double mx = wave_max(umax);
     const int nf = __any(nonfinite) ? 1 : 0;
