@@ -56,12 +56,18 @@ struct PassKind {
   static constexpr int value = K;
 };
 
+// Value of v on lane addr/4 of the wavefront (ds_bpermute: the LDS
+// crossbar without a memory round trip); every lane must be active.
 template <typename TS>
-struct PcrBuf {
-  TS a[2][kWave], c[2][kWave], d[2][kWave], rb[2][kWave];
-  TS oa[kWave], oc[kWave], od[kWave], orb[kWave];   // odd equations
-  double xe[kWave + 1];                               // even unknowns
-};
+__device__ __forceinline__ TS lane_get(TS v, int addr) {
+  if constexpr (sizeof(TS) == 8) {
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+  }
+}
 
 // Solve the symmetric tridiagonal system with diagonal Td[0..n),
 // off-diagonal To[k] = T_{k,k+1} and right-hand side rhs by ONE wavefront
@@ -70,13 +76,12 @@ struct PcrBuf {
 // unknowns (each even equation takes its two odd neighbours), parallel cyclic
 // reduction solves the <= 64 even equations, one per lane, and the odd
 // unknowns follow by back-substitution.  One reciprocal per equation and level.
-// No lane branches: an equation's coupling to a neighbour that does not exist
-// is exactly zero (and lanes past the last even equation hold identity rows),
-// so every lane reads clamped, in-range neighbours and adds zero terms; all
-// reads of a level are issued together.
+// Neighbours' coefficients move lane to lane with ds_bpermute.  No lane
+// branches: an equation's coupling to a neighbour that does not exist is
+// exactly zero (and lanes past the last even equation hold identity rows),
+// so every lane fetches a clamped, in-range neighbour and adds zero terms.
 template <typename TS>
-__device__ void pcr_solve(int n, const double* Td, const double* To, const double* rhs,
-                          double* x, PcrBuf<TS>& B) {
+__device__ void pcr_solve(int n, const double* Td, const double* To, const double* rhs, double* x) {
   const int l = threadIdx.x & (kWave - 1);
   const int j0 = 2 * l, j1 = 2 * l + 1;
   const int m = (n + 1) / 2;   // even equations
@@ -94,14 +99,12 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   const TS c1 = (v1 && j1 + 1 < n) ? (TS)to1 : (TS)0;
   const TS d1 = v1 ? (TS)rh1 : (TS)0;
   const TS r1 = rcp_nr(b1);
-  B.oa[l] = a1; B.oc[l] = c1; B.od[l] = d1; B.orb[l] = r1;
-  wave_sync();
   // even equation 2l with odd neighbours 2l-1 (lane l-1; a0 = 0 on lane 0)
   // and 2l+1 (own)
   TS A, Bv, C, Dv;
   {
-    const int lm = l > 0 ? l - 1 : 0;
-    const TS orb = B.orb[lm], oa = B.oa[lm], oc = B.oc[lm], od = B.od[lm];
+    const int am = (l > 0 ? l - 1 : 0) * 4;
+    const TS orb = lane_get(r1, am), oa = lane_get(a1, am), oc = lane_get(c1, am), od = lane_get(d1, am);
     const TS al = -a0 * orb, ga = -c0 * r1;
     A = al * oa;
     C = ga * c1;
@@ -110,14 +113,11 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   }
   if (l >= m) { A = 0; Bv = 1; C = 0; Dv = 0; }
   TS rB = rcp_nr(Bv);
-  int cur = 0;
   for (int s = 1; s < m; s <<= 1) {
-    B.a[cur][l] = A; B.c[cur][l] = C; B.d[cur][l] = Dv; B.rb[cur][l] = rB;
-    wave_sync();
     // A = 0 when l - s < 0 and C = 0 when l + s >= m: those terms add zero
-    const int lo = l >= s ? l - s : l, hi = l + s < kWave ? l + s : l;
-    const TS rbm = B.rb[cur][lo], am = B.a[cur][lo], cm = B.c[cur][lo], dm = B.d[cur][lo];
-    const TS rbp = B.rb[cur][hi], ap = B.a[cur][hi], cp = B.c[cur][hi], dpv = B.d[cur][hi];
+    const int lo = (l >= s ? l - s : l) * 4, hi = (l + s < kWave ? l + s : l) * 4;
+    const TS rbm = lane_get(rB, lo), am = lane_get(A, lo), cm = lane_get(C, lo), dm = lane_get(Dv, lo);
+    const TS rbp = lane_get(rB, hi), ap = lane_get(A, hi), cp = lane_get(C, hi), dpv = lane_get(Dv, hi);
     const TS al = -A * rbm, ga = -C * rbp;
     A = al * am;
     C = ga * cp;
@@ -126,15 +126,13 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
     Dv += al * dm;
     Dv += ga * dpv;
     rB = rcp_nr(Bv);
-    cur ^= 1;
   }
   const double xe = (double)(Dv * rB);
-  B.xe[l] = xe;
-  if (l == kWave - 1) B.xe[kWave] = 0.0;
-  wave_sync();
+  // even unknown 2l+2 from lane l+1 (none past the last lane)
+  const double xnb = lane_get<double>(xe, (l + 1 < kWave ? l + 1 : l) * 4);
   if (v0) x[j0] = xe;
   if (v1) {
-    const TS xn = (j1 + 1 < n) ? (TS)B.xe[l + 1] : (TS)0;
+    const TS xn = (j1 + 1 < n) ? (TS)xnb : (TS)0;
     x[j1] = (double)((d1 - a1 * (TS)xe - c1 * xn) * r1);
   }
   wave_sync();
@@ -220,7 +218,6 @@ struct SlabSh {
 template <int NXM, int UHN, typename TS>
 struct SlabLds {
   SlabSh<NXM> sh;
-  PcrBuf<TS> pcr;
   double uhl[UHN];   // u_hat (forward) or u* + grad_u (adjoint)
 };
 
@@ -249,7 +246,6 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
 
   __shared__ SlabLds<NXM, UHN, TS> lds;
   SlabSh<NXM>& sh = lds.sh;
-  PcrBuf<TS>& pcr = lds.pcr;
   double* const uhl = lds.uhl;
 
   const double* aux = A.aux + D.aux_off;
@@ -625,7 +621,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         }
         wave_sync();
         if (!done && nr > 0) {
-          pcr_solve<TS>(nr, sh.Td, sh.To, sh.r, sh.lamp, pcr);
+          pcr_solve<TS>(nr, sh.Td, sh.To, sh.r, sh.lamp);
           if constexpr (sizeof(TS) != sizeof(double)) {
             // float32 solve, float64 residual and refinement
             constexpr int max_ref = 4;
@@ -662,7 +658,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
               const double target = bwd ? 1e-15 * rn
                                         : (hinf > 1e-6 ? 1e-6 * rn : fmax(1e-15 * rn, 0.1 * A.opt.tol_h));
               if (!(resmax > target)) break;
-              pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
+              pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx);
 #pragma unroll
               for (int e = 0; e < 2; ++e) {
                 const int k = lane + kWave * e;
@@ -730,7 +726,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           wave_sync();
           for (int k = lane; k < nr; k += kWave) sh.res[k] = row_h(k) - (k == 0 ? sh.scal[3] : 0.0);
           wave_sync();
-          if (nr > 0) pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx, pcr);
+          if (nr > 0) pcr_solve<TS>(nr, sh.Td, sh.To, sh.res, sh.dx);
           const double z0 = nr > 0 ? sh.dx[0] : 0.0;
           const double W0 = sh.W[0];
           if (grp == 0) {
