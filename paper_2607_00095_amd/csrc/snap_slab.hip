@@ -49,7 +49,7 @@ namespace {
 constexpr int kMaxNt = 128;
 constexpr double kWFloor = 0.1;
 
-// kinds of slab-sum pass (see the kernel)
+// compile-time tags: kinds of slab-sum pass (see the kernel), and flags
 constexpr int kPoint = 0, kStep = 1;
 template <int K>
 struct PassKind {
@@ -344,7 +344,9 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       const double hh = ok ? uu + pst[r][j] : 0.0;   // u_hat, or u* + grad_u
       u[r][j] = uu;
       pst[r][j] = 0.0;
-      if (ok) uhl[eidx(r, j)] = hh;
+      // full-width grids also zero the staging slots of slabs past nt (they
+      // lie inside the array), which the unguarded trial pass reads
+      if (ok || nx == NXM) uhl[eidx(r, j)] = hh;
       umax = fmax(umax, fabs(hh));
       nonfinite |= !finite(hh) || !finite(uu);
     }
@@ -408,50 +410,60 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       // The accumulators start at -0, which the first add folds away.
       const double gam = a1 * lk, bet = a0 * lk + lkm;
       double Su = -0.0, Suu = -0.0, Sg = -0.0, Sug = -0.0, sar = -0.0, hmx = 0, h1 = -0.0, lpm = 0;
-#pragma unroll
-      for (int j = 0; j < XPL; ++j) {
-        const int x = xat(j);
-        if (kv && x < nx) {
-          double uu = u[r][j];
-          const double uh = uhl[eb + G * j];
-          double bx = bet;
-          if (ic) {
-            double lm;
-            if constexpr (step) {
-              lm = sh.lamic[xs + G * j] + (W0 * sh.ric[xs + G * j] - (a0 + a1 * uu) * dl0);
-              sh.lampic[xs + G * j] = lm;
-              lpm = fmax(lpm, fabs(lm));
-            } else {
-              lm = lamicv[xs + G * j];
-            }
-            bx = a0 * lk + lm;
-          }
+      // one element (round r, j); IC: the slab-0 lanes' IC terms may apply
+      auto elem = [&](int j, auto icc) {
+        constexpr bool IC = decltype(icc)::value;
+        double uu = u[r][j];
+        const double uh = uhl[eb + G * j];
+        double bx = bet;
+        if (IC && ic) {
+          double lm;
           if constexpr (step) {
-            const double d = uu - uh;
-            const double jt = fma(uu, gam, d) + bx;
-            const double p = -jt * rWc;
-            pst[r][j] = p;
-            pp = fma(p, p, pp);
-            dd = fma(d, p, dd);
-            uu = uu + 1.0 * p;
+            lm = sh.lamic[xs + G * j] + (W0 * sh.ric[xs + G * j] - (a0 + a1 * uu) * dl0);
+            sh.lampic[xs + G * j] = lm;
+            lpm = fmax(lpm, fabs(lm));
+          } else {
+            lm = lamicv[xs + G * j];
           }
-          Su += uu;
-          Suu = fma(uu, uu, Suu);
-          const double g = fma(uu, gam, uu - uh) + bx;
-          Sg += g;
-          Sug = fma(uu, g, Sug);
-          st = max_abs(st, g);
-          if (ic) {
-            const double a = a0 + a1 * uu;
-            const double gi = sh.gic[xs + G * j];
-            const double hic = bwd ? 0.0 : uu - gi;
-            const double ric = hic - g * rW0;
-            sh.ric[xs + G * j] = ric;
-            sar += a * ric;
-            hmx = fmax(hmx, fabs(hic));
-            h1 += fabs(hic);
-          }
+          bx = a0 * lk + lm;
         }
+        if constexpr (step) {
+          const double d = uu - uh;
+          const double jt = fma(uu, gam, d) + bx;
+          const double p = -jt * rWc;
+          pst[r][j] = p;
+          pp = fma(p, p, pp);
+          dd = fma(d, p, dd);
+          uu = uu + 1.0 * p;
+        }
+        Su += uu;
+        Suu = fma(uu, uu, Suu);
+        const double g = fma(uu, gam, uu - uh) + bx;
+        Sg += g;
+        Sug = fma(uu, g, Sug);
+        st = max_abs(st, g);
+        if (IC && ic) {
+          const double a = a0 + a1 * uu;
+          const double gi = sh.gic[xs + G * j];
+          const double hic = bwd ? 0.0 : uu - gi;
+          const double ric = hic - g * rW0;
+          sh.ric[xs + G * j] = ric;
+          sar += a * ric;
+          hmx = fmax(hmx, fabs(hic));
+          h1 += fabs(hic);
+        }
+      };
+      // Full-width grid (nx = G*XPL) outside round 0 of wavefront 0: the only
+      // slots outside the grid are whole slabs past nt, which hold u = 0, a
+      // zero-filled staging row and zero multipliers, so every term they
+      // add is exactly zero and the elements need no guard.
+      if (step && nx == NXM && !(r == 0 && w == 0)) {
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) elem(j, PassKind<0>{});
+      } else {
+#pragma unroll
+        for (int j = 0; j < XPL; ++j)
+          if (kv && xat(j) < nx) elem(j, PassKind<1>{});
       }
       if constexpr (G == 16) {
         // a group is a row: one transposed reduction, four lanes write
