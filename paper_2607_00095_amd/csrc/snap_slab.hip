@@ -532,6 +532,14 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       const int qi = lane < NW ? lane : 0;
       const bool qv = lane < NW;
       const double qst = sh.red[qi][0], qpp = sh.red[qi][1], qdd = sh.red[qi][2];
+      // a pending step's multipliers and its IC rows' max |lam+| are read with
+      // the sums, so an accepted step needs no further LDS round trip
+      const double sc5 = sh.scal[5];
+      static_assert(kMaxNt == 2 * kWave, "two rows per lane");
+      const double lp0 = sh.lamp[lane], lp1 = sh.lamp[lane + kWave];
+      double lpic[NXM / kWave];
+#pragma unroll
+      for (int e = 0; e < NXM / kWave; ++e) lpic[e] = sh.lampic[lane + kWave * e];
       // rows k = lane and lane + 64 (nr <= 127): h from the slab sums, once
       double hk[2];
 #pragma unroll
@@ -545,16 +553,18 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       }
       double h1 = (lane == 0) ? sh.scal[2] : 0.0;
       h1 += fabs(hk[0]) + fabs(hk[1]);
+      // the three reductions are independent (the merit terms are formed even
+      // when no step is pending; they are then unused)
       h1 = wave_sum(h1);
+      const double pp = wave_sum(qv ? qpp : 0.0), dd = wave_sum(qv ? qdd : 0.0);
       if (pend) {
         // penalty mu >= 1.1 ||lam+||_inf of the pending step (IC rows' part
         // from the trial pass)
-        mu = bcast_first(fmax(mu, 1.1 * fmax(lmrow, sh.scal[5]) + 1e-8));
+        mu = bcast_first(fmax(mu, 1.1 * fmax(lmrow, sc5) + 1e-8));
         // Armijo test of phi = 1/2||u - u_hat||^2 + mu||h||_1 at alpha = 1; the
         // change is formed from differences, d.p + p.p/2 + mu(||h_t||_1 - ||h||_1),
         // so rounding of the large sums in phi never decides.  Local phase
         // (||h||_inf <= 1e-6): full Newton steps.
-        const double pp = wave_sum(qv ? qpp : 0.0), dd = wave_sum(qv ? qdd : 0.0);
         const double dphi = dd - mu * h1cur;
         const double dphit = dd + 0.5 * pp + mu * (h1 - h1cur);
         acc = (dphit <= 1e-4 * dphi) || !(dphi < 0.0) || hinf <= 1e-6;
@@ -565,8 +575,6 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           // (u += p is applied by every wavefront after the barrier).  Rows
           // past nr hold lam+ = 0 and W = 1 throughout, so all 128 entries
           // are rewritten without a branch.
-          static_assert(kMaxNt == 2 * kWave, "two rows per lane");
-          const double lp0 = sh.lamp[lane], lp1 = sh.lamp[lane + kWave];
 #pragma unroll
           for (int e = 0; e < 2; ++e) {
             const int k = lane + kWave * e;
@@ -577,7 +585,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
             sh.rW[k] = rcp_nr(wk);
           }
 #pragma unroll
-          for (int e = 0; e < NXM / kWave; ++e) sh.lamic[lane + kWave * e] = sh.lampic[lane + kWave * e];
+          for (int e = 0; e < NXM / kWave; ++e) sh.lamic[lane + kWave * e] = lpic[e];
           wave_sync();
         } else {
           bt = 1;
