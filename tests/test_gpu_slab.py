@@ -55,6 +55,30 @@ def test_fisher_kpp_matches_oracle(nx, nt):
     _check_against_oracle(b, res, range(len(b)), U_TOL_FP64, 1e-8)
 
 
+# Grids as wide as their kernel class (Nx = 64 or 128) run the step/trial
+# pass without per-element guards; slabs past Nt then contribute exactly zero.
+# Nt is chosen so the partial last round falls on different wavefronts, or
+# is absent (Nt = 32 / 128: whole rounds only).
+@pytest.mark.parametrize("nx,nt", [(64, 20), (64, 32), (64, 77), (64, 128),
+                                   (128, 33), (128, 65), (128, 127), (128, 128)])
+def test_fisher_kpp_full_width_grids(nx, nt):
+    b = synthgen.fisher_kpp_batch(batch=2, nx=nx, nt=nt, seed=3 * nx + nt)
+    res = gpu_project(b)
+    _check_against_oracle(b, res, range(len(b)), U_TOL_FP64, 1e-8)
+
+
+def test_fisher_kpp_full_width_adjoint():
+    b = synthgen.fisher_kpp_batch(batch=2, nx=128, nt=65, seed=11)
+    res = gpu_project(b)
+    grad = synthgen.upstream_grad(b, seed=4)
+    g_gpu, st = gpu_backward(res, grad)
+    for s, smp in enumerate(b.samples):
+        vo = b.var_off[s]
+        u_o, lam_o = project_sample(family_of(smp), smp.uhat.reshape(-1))
+        g_o = adjoint_sample(family_of(smp), u_o, lam_o, grad[vo:vo + smp.n])
+        assert rel_err(g_gpu[vo:vo + smp.n], g_o) <= 1e-10
+
+
 def test_fisher_kpp_full_config_sampled():
     b = synthgen.make("fisher_kpp")
     res = gpu_project(b)
