@@ -210,7 +210,7 @@ struct SlabSh {
   double red2[16][2];    // load: max|u_hat|, non-finite; second-order trial: q.q, (u-u_hat).q
   double scal[6];        // IC rows: sum a_0 r_ic, max|h_ic|, sum|h_ic|; [3] second-order
                          // sum a_0 h_ic; [4] dlam_0 of the pending step; [5] max|lam+_ic|
-  int flag[4];           // done, accepted, backtrack, line-search verdict
+  int flag[5];           // done, accepted, backtrack, line-search verdict, trial written
 };
 
 // The kernel's LDS in one object, the large u_hat staging last, so that every
@@ -379,6 +379,12 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   //           for the line search and its maximum kept for the penalty);
   // Per slab: sum u, sum u^2, sum g, sum u g, and the IC rows'
   // r_ic = h_ic - g/W_0 (W_0 of the multipliers the sums describe).
+  // In the local phase (||h||_inf <= 1e-6 at the current point) the full step
+  // is always accepted, so its trial point u + p can go to the output right
+  // after the step pass: it is the next iterate. `written` records that the
+  // output holds the current iterate.
+  bool spec = false, written = false;
+  double* const uout = A.u + vo;
   auto sums_pass = [&](const double* lamv, const double* lamicv, auto kind) {
     constexpr int M = decltype(kind)::value;
     constexpr bool step = M == kStep;
@@ -428,6 +434,9 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           bx = a0 * lk + lm;
         }
         if constexpr (step) {
+          // the trial point is u + p with p rounded first (no contraction),
+          // the same value the accepted step gives u
+#pragma clang fp contract(off)
           const double d = uu - uh;
           const double jt = fma(uu, gam, d) + bx;
           const double p = -jt * rWc;
@@ -707,10 +716,14 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           lmrow = bcast_first(wave_max(lm));
         }
       }
-      if (lane == 0) { sh.flag[0] = done; sh.flag[1] = acc; sh.flag[2] = bt | (soc << 1); }
+      if (lane == 0) {
+        sh.flag[0] = done; sh.flag[1] = acc; sh.flag[2] = bt | (soc << 1);
+        sh.flag[4] = !bwd && !bt && hinf <= 1e-6;   // the coming step will be accepted
+      }
     }
     lds_barrier();
     const int done = sh.flag[0], acc = sh.flag[1], bt = sh.flag[2] & 1, soc_try = sh.flag[2] >> 1;
+    spec = sh.flag[4] != 0;
     if (acc) {
 #pragma unroll
       for (int r = 0; r < RMAX; ++r)
@@ -940,21 +953,40 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
       break;
     }
     // ------------------------------------------------ step and trial point at alpha = 1
+    written = spec;
     sums_pass(sh.lamp, sh.lampic, PassKind<kStep>{});
+    if (spec) {
+      // the coming acceptance gives u + p: write it now (the same operation
+      // as the update below), the stores drain while wavefront 0 tests
+      const int xs = opaque(sub), gq = opaque(grp);
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        const int k = slab_of(gq, r);
+#pragma unroll
+        for (int j = 0; j < XPL; ++j) {
+          const int x = xat(j);
+          if (k < nt && x < nx) uout[k * nx + xs + G * j] = u[r][j] + 1.0 * pst[r][j];
+        }
+      }
+    }
     lds_barrier();
     pend = true;
   }
 
   // ---------------------------------------------------------------- outputs
   if (!bwd) {
+    // (the field is already in place when the last step pass wrote its trial
+    // point and that step was accepted, which the local phase guarantees)
     const int xs = opaque(sub), gq = opaque(grp);
+    if (!written) {
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      const int k = slab_of(gq, r);
+      for (int r = 0; r < RMAX; ++r) {
+        const int k = slab_of(gq, r);
 #pragma unroll
-      for (int j = 0; j < XPL; ++j) {
-        const int x = xat(j);
-        if (k < nt && x < nx) A.u[vo + k * nx + xs + G * j] = u[r][j];
+        for (int j = 0; j < XPL; ++j) {
+          const int x = xat(j);
+          if (k < nt && x < nx) A.u[vo + k * nx + xs + G * j] = u[r][j];
+        }
       }
     }
     for (int x = tid; x < nx; x += NT) A.lam[D.row_off + x] = sh.lamic[x];
