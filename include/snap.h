@@ -81,8 +81,12 @@ enum snap_flags {
                                 when they change); the plan keeps one graph per
                                 direction.  Needs a non-null stream: on the
                                 null stream the call runs its launches
-                                directly.  Calls with this flag on one plan
-                                from several host threads are serialized. */
+                                directly.  A call that is a single kernel
+                                launch (a plan of one slab-row group) also
+                                runs directly: a graph of one launch only adds
+                                the replay's overhead.  Calls with this flag on
+                                one plan from several host threads are
+                                serialized. */
   SNAP_FLAG_AUTOTUNE = 4,    /* snap_plan_create times every launch shape that
                                 can run a group of samples (lanes per time slab
                                 and rounds for the slab-row families; wavefronts

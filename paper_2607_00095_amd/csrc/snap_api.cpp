@@ -457,6 +457,8 @@ static bool same_call(const KernelArgs& x, const KernelArgs& y) {
 // captured through its events).
 static int run_graph(snap_plan plan, const KernelArgs& a, hipStream_t st) {
   if (st == nullptr) return run(plan, a, st);   // the null stream cannot be captured
+  // one slab-row group is one kernel launch: a graph would only add its replay
+  if (plan->groups.size() == 1 && plan->groups[0].kind == 0) return run(plan, a, st);
   std::lock_guard<std::mutex> lock(plan->graph_mu);
   GraphSlot& g = plan->graphs[a.backward ? 1 : 0];
   if (!g.exec || !same_call(g.key, a)) {
