@@ -210,7 +210,7 @@ struct SlabSh {
   double red2[16][2];    // load: max|u_hat|, non-finite; second-order trial: q.q, (u-u_hat).q
   double scal[6];        // IC rows: sum a_0 r_ic, max|h_ic|, sum|h_ic|; [3] second-order
                          // sum a_0 h_ic; [4] dlam_0 of the pending step; [5] max|lam+_ic|
-  int flag[5];           // done, accepted, backtrack, line-search verdict, trial written
+  int flag[5];           // done, accepted, backtrack, line-search outcome, local phase
 };
 
 // The kernel's LDS in one object, the large u_hat staging last, so that every
