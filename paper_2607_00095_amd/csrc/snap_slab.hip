@@ -69,6 +69,22 @@ __device__ __forceinline__ TS lane_get(TS v, int addr) {
   }
 }
 
+// Value of v on lane l-1 / l+1 (lane 0 / lane 63: its own), by DPP
+// whole-wavefront shifts (wave_shr:1 / wave_shl:1): no LDS round trip.
+template <typename TS, int CTRL>
+__device__ __forceinline__ TS lane_shift(TS v) {
+  if constexpr (sizeof(TS) == 8) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false));
+  } else {
+    const int x = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false));
+  }
+}
+template <typename TS> __device__ __forceinline__ TS lane_prev(TS v) { return lane_shift<TS, 0x138>(v); }
+template <typename TS> __device__ __forceinline__ TS lane_next(TS v) { return lane_shift<TS, 0x130>(v); }
+
 // Solve the symmetric tridiagonal system with diagonal Td[0..n),
 // off-diagonal To[k] = T_{k,k+1} and right-hand side rhs by ONE wavefront
 // (n <= 128), in precision TS; the result goes to x (LDS).  Lane l holds
@@ -76,7 +92,8 @@ __device__ __forceinline__ TS lane_get(TS v, int addr) {
 // unknowns (each even equation takes its two odd neighbours), parallel cyclic
 // reduction solves the <= 64 even equations, one per lane, and the odd
 // unknowns follow by back-substitution.  One reciprocal per equation and level.
-// Neighbours' coefficients move lane to lane with ds_bpermute.  No lane
+// Neighbours' coefficients move lane to lane by DPP shifts at distance 1
+// and by ds_bpermute beyond.  No lane
 // branches: an equation's coupling to a neighbour that does not exist is
 // exactly zero (and lanes past the last even equation hold identity rows),
 // so every lane fetches a clamped, in-range neighbour and adds zero terms.
@@ -103,8 +120,7 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   // and 2l+1 (own)
   TS A, Bv, C, Dv;
   {
-    const int am = (l > 0 ? l - 1 : 0) * 4;
-    const TS orb = lane_get(r1, am), oa = lane_get(a1, am), oc = lane_get(c1, am), od = lane_get(d1, am);
+    const TS orb = lane_prev(r1), oa = lane_prev(a1), oc = lane_prev(c1), od = lane_prev(d1);
     const TS al = -a0 * orb, ga = -c0 * r1;
     A = al * oa;
     C = ga * c1;
@@ -113,11 +129,9 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
   }
   if (l >= m) { A = 0; Bv = 1; C = 0; Dv = 0; }
   TS rB = rcp_nr(Bv);
-  for (int s = 1; s < m; s <<= 1) {
-    // A = 0 when l - s < 0 and C = 0 when l + s >= m: those terms add zero
-    const int lo = (l >= s ? l - s : l) * 4, hi = (l + s < kWave ? l + s : l) * 4;
-    const TS rbm = lane_get(rB, lo), am = lane_get(A, lo), cm = lane_get(C, lo), dm = lane_get(Dv, lo);
-    const TS rbp = lane_get(rB, hi), ap = lane_get(A, hi), cp = lane_get(C, hi), dpv = lane_get(Dv, hi);
+  // one PCR level with the neighbours' (rb, a, c, d) at l - s and l + s;
+  // A = 0 when l - s < 0 and C = 0 when l + s >= m: those terms add zero
+  auto level = [&](TS rbm, TS am, TS cm, TS dm, TS rbp, TS ap, TS cp, TS dpv) {
     const TS al = -A * rbm, ga = -C * rbp;
     A = al * am;
     C = ga * cp;
@@ -126,10 +140,18 @@ __device__ void pcr_solve(int n, const double* Td, const double* To, const doubl
     Dv += al * dm;
     Dv += ga * dpv;
     rB = rcp_nr(Bv);
+  };
+  if (1 < m)
+    level(lane_prev(rB), lane_prev(A), lane_prev(C), lane_prev(Dv),
+          lane_next(rB), lane_next(A), lane_next(C), lane_next(Dv));
+  for (int s = 2; s < m; s <<= 1) {
+    const int lo = (l >= s ? l - s : l) * 4, hi = (l + s < kWave ? l + s : l) * 4;
+    level(lane_get(rB, lo), lane_get(A, lo), lane_get(C, lo), lane_get(Dv, lo),
+          lane_get(rB, hi), lane_get(A, hi), lane_get(C, hi), lane_get(Dv, hi));
   }
   const double xe = (double)(Dv * rB);
   // even unknown 2l+2 from lane l+1 (none past the last lane)
-  const double xnb = lane_get<double>(xe, (l + 1 < kWave ? l + 1 : l) * 4);
+  const double xnb = lane_next(xe);
   if (v0) x[j0] = xe;
   if (v1) {
     const TS xn = (j1 + 1 < n) ? (TS)xnb : (TS)0;
