@@ -312,3 +312,93 @@ def family_of(sample, **kw):
 
 def constraint_types(family: int):
     return FAMILIES[family].types
+
+
+def real_fourier_basis(n):
+    """Orthonormal real Fourier basis of R^n on the periodic grid x = 0..n-1
+    (n even), as the columns of an n x n matrix, and the frequency of each
+    column: 1/sqrt(n); sqrt(2/n) cos(2 pi k x/n), k = 1..n/2-1; (-1)^x/sqrt(n);
+    sqrt(2/n) sin(2 pi k x/n), k = 1..n/2-1.  Every column is an eigenvector of
+    the periodic second difference, with eigenvalue -4 sin^2(pi k/n)."""
+    if n % 2:
+        raise ValueError("the real Fourier basis here needs an even grid")
+    x = np.arange(n)
+    half = n // 2
+    Q = np.empty((n, n))
+    freq = np.empty(n, dtype=np.int64)
+    Q[:, 0], freq[0] = 1.0 / np.sqrt(n), 0
+    for k in range(1, half):
+        Q[:, k], freq[k] = np.sqrt(2.0 / n) * np.cos(2 * np.pi * k * x / n), k
+        Q[:, half + k], freq[half + k] = np.sqrt(2.0 / n) * np.sin(2 * np.pi * k * x / n), k
+    Q[:, half], freq[half] = (-1.0) ** x / np.sqrt(n), half
+    return Q, freq
+
+
+class Diff2DEnergySpectral:
+    """The 2D diffusion + per-frame energy family written in the orthonormal
+    real Fourier basis of each frame: v_t = Q^T u_t Q (Q = real_fourier_basis,
+    rows y, columns x), residual rows rotated by the same Q.  Because the
+    periodic 5-point Laplacian is diagonal in that basis, the rows are
+
+      residual rows  a(j,i) v_{k+1}(j,i) - v_k(j,i)      k = 0..Nt-2, modes (j, i)
+      energy rows    sum_{j,i} v_t(j,i)^2 - E_t          t = 0..Nt-1
+
+    with a(j,i) = 1 + dt*kappa*(4/dx^2)(sin^2(pi f_j/N) + sin^2(pi f_i/N)).
+    The change of basis is orthogonal, so 1/2||u - u_hat||^2 = 1/2||v - v_hat||^2,
+    the projection of v_hat is the transform of the projection of u_hat, and the
+    residual multipliers transform back by the same Q (energy multipliers are
+    unchanged)."""
+    types = ("residual", "energy")
+
+    def __init__(self, phys):
+        if phys.nx != phys.ny:
+            raise ValueError("square grids only")
+        self.phys = phys
+        self.nx = self.ny = phys.nx
+        self.nt = phys.nt
+        self.np_ = phys.np_
+        self.n, self.m = phys.n, phys.m
+        self.E = phys.E
+        self.Q, f = real_fourier_basis(self.nx)
+        s = np.sin(np.pi * f / self.nx) ** 2
+        self.a = 1.0 + phys.dt * phys.kappa * (4.0 / (phys.dx * phys.dx)) * (s[:, None] + s[None, :])
+
+    # orthogonal maps between the physical and spectral coordinates
+    def to_spectral(self, u):
+        U = np.asarray(u).reshape(-1, self.ny, self.nx)
+        return np.einsum("yj,tyx,xi->tji", self.Q, U, self.Q).reshape(-1)
+
+    def from_spectral(self, v):
+        V = np.asarray(v).reshape(-1, self.ny, self.nx)
+        return np.einsum("yj,tji,xi->tyx", self.Q, V, self.Q).reshape(-1)
+
+    def lam_from_spectral(self, lam):
+        k = (self.nt - 1) * self.np_
+        return np.concatenate([self.from_spectral(lam[:k]), lam[k:]])
+
+    def h(self, v):
+        V = v.reshape(self.nt, self.np_)
+        a = self.a.reshape(-1)
+        res = a[None, :] * V[1:] - V[:-1]
+        energy = (V * V).sum(axis=1) - self.E
+        return np.concatenate([res.reshape(-1), energy])
+
+    def jac(self, v):
+        V = v.reshape(self.nt, self.np_)
+        npt, nt = self.np_, self.nt
+        a = self.a.reshape(-1)
+        K, P = np.meshgrid(np.arange(nt - 1), np.arange(npt), indexing="ij")
+        row = K * npt + P
+        T, P2 = np.meshgrid(np.arange(nt), np.arange(npt), indexing="ij")
+        rows = np.concatenate([row.ravel(), row.ravel(), ((nt - 1) * npt + T).ravel()])
+        cols = np.concatenate([((K + 1) * npt + P).ravel(), (K * npt + P).ravel(), (T * npt + P2).ravel()])
+        vals = np.concatenate([np.broadcast_to(a, K.shape).ravel(), -np.ones(K.size), 2.0 * V.ravel()])
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.m, self.n))
+
+    def hess(self, v, lam):
+        lam_e = np.asarray(lam[(self.nt - 1) * self.np_:])
+        return sp.diags(np.repeat(2.0 * lam_e, self.np_))
+
+    def split(self, r):
+        k = (self.nt - 1) * self.np_
+        return {"residual": r[:k], "energy": r[k:]}

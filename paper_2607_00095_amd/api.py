@@ -225,20 +225,37 @@ def stats_to_numpy(stats: torch.Tensor, batch: int) -> np.ndarray:
 
 
 class SnapProject(torch.autograd.Function):
-    """u* = P(u_hat); backward gives the implicit-function VJP d u*/d u_hat."""
+    """u* = P(u_hat); backward gives the implicit-function VJP d u*/d u_hat.
+
+    u_hat holds exactly plan.total_vars values (any shape); u* and the
+    gradient have u_hat's shape.  The backward checks the forward's
+    per-sample status (one device-to-host copy of the stats) and raises
+    SnapError if a sample did not converge, since the implicit-function
+    gradient only holds at a KKT point; pass allow_unconverged=True to get
+    the gradient at the returned points anyway."""
 
     @staticmethod
-    def forward(ctx, uhat, aux, plan: Plan):
-        u, lam, st, ws = project(plan, uhat.contiguous(), aux)
+    def forward(ctx, uhat, aux, plan: Plan, allow_unconverged: bool = False):
+        if uhat.numel() != plan.total_vars:
+            raise SnapError(f"u_hat has {uhat.numel()} values, the plan has {plan.total_vars}")
+        u, lam, st, ws = project(plan, uhat.detach().contiguous().view(-1), aux)
         ctx.plan = plan
-        ctx.save_for_backward(u, lam, aux if aux is not None else torch.empty(0), ws)
-        ctx.stats = st
-        return u[: plan.total_vars]
+        ctx.shape = uhat.shape
+        ctx.allow = allow_unconverged
+        ctx.save_for_backward(u, lam, aux if aux is not None else torch.empty(0), ws, st)
+        return u[: plan.total_vars].view(uhat.shape)
 
     @staticmethod
     def backward(ctx, grad_u):
-        u, lam, aux, ws = ctx.saved_tensors
+        u, lam, aux, ws, st = ctx.saved_tensors
         plan = ctx.plan
+        if not ctx.allow and plan.batch > 0:
+            status = stats_to_numpy(st, plan.batch)["status"]
+            if (status != 0).any():
+                bad = np.flatnonzero(status != 0)
+                raise SnapError(f"{bad.size} sample(s) did not converge in the forward "
+                                f"(first: {bad[0]}, status {status_name(status[bad[0]])}); "
+                                "their implicit-function gradient is undefined")
         g, _ = project_backward(plan, u, lam, aux if aux.numel() else None, ws,
-                                grad_u.contiguous().to(torch.float64))
-        return g[: plan.total_vars], None, None
+                                grad_u.contiguous().view(-1).to(torch.float64))
+        return g[: plan.total_vars].view(ctx.shape), None, None, None

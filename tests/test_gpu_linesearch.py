@@ -1,58 +1,41 @@
 """Backtracking line search on strongly nonlinear Fisher-KPP samples.
 
 Large dt*rho (0.45-0.55 with rho up to 2) makes the logistic budget rows
-strongly nonlinear: on these samples the full Newton step from u_hat does not
-decrease the l1 merit, so the kernels must halve the step (alpha < 1) before
-converging.  The samples are those on which the oracle's damped Newton
-iteration also converges, and both must reach the same KKT point.
+strongly nonlinear: on many of these samples the full Newton step from u_hat
+does not decrease the l1 merit, so the kernels must halve the step
+(alpha < 1) before converging.  Every sample of the 15 seeded batches
+(60 samples) is compared with the oracle's SQP point.
 """
 import numpy as np
 import pytest
 
 import paper_2607_00095_amd as snap
 import synthgen
-from gpu_helpers import gpu_project, rel_err
-from oracle.kkt import project_batch
-from oracle.metric import max_violation
+from gpu_helpers import check_samples, gpu_project
 
 pytestmark = pytest.mark.gpu
 
-# (dt, seed, sample index) of fisher_kpp_batch(batch=4, nx=20, nt=8)
-PICKS = [(0.5, 4, 0), (0.5, 5, 0), (0.45, 4, 0), (0.55, 2, 2), (0.5, 1, 2), (0.55, 5, 0)]
+STRONG = [(dt, seed) for dt in (0.45, 0.5, 0.55) for seed in range(1, 6)]
 
 
 def _batch():
-    smp = [synthgen.fisher_kpp_batch(batch=4, nx=20, nt=8, seed=s, dt=dt).samples[i]
-           for dt, s, i in PICKS]
+    smp = [s for dt, seed in STRONG
+           for s in synthgen.fisher_kpp_batch(batch=4, nx=20, nt=8, seed=seed, dt=dt).samples]
     return synthgen.Batch(smp, name="fisher_kpp").pack()
 
 
-@pytest.mark.parametrize("precision,tol", [(snap.PREC_FP64, 1e-10), (snap.PREC_MIXED, 1e-6)])
-def test_backtracking_reaches_oracle_point(precision, tol):
+@pytest.mark.parametrize("precision,tol,lam_tol", [(snap.PREC_FP64, 1e-10, 1e-8),
+                                                   (snap.PREC_MIXED, 1e-6, 1e-4)])
+def test_backtracking_reaches_oracle_point(precision, tol, lam_tol):
     b = _batch()
-    res = gpu_project(b, snap.Options(precision=precision))
+    res = gpu_project(b, snap.Options(precision=precision, max_newton=60))
     st = res["stats"]
-    assert (st["status"] == 0).all(), st["status"]
+    print("newton iters", st["newton_iters"].tolist(), "backtracks", st["ls_backtracks"].tolist())
     assert st["ls_backtracks"].sum() > 0          # the halving path ran
-    assert max_violation(b, res["u_np"]).max() <= 1e-8
-    u_o, lam_o, _ = project_batch(b)
-    for s, o in zip(b.samples, b.var_off):
-        assert rel_err(res["u_np"][o:o + s.n], u_o[o:o + s.n]) <= tol
-
-
-# samples on which the one-try second-order correction is taken and the
-# iteration still converges (on the others it slows or stalls convergence,
-# which is why it is off by default)
-SOC_PICKS = [PICKS[1], PICKS[3], PICKS[4]]
+    check_samples(b, res, range(len(b)), tol, lam_tol)
 
 
 def test_second_order_correction_option():
-    smp = [synthgen.fisher_kpp_batch(batch=4, nx=20, nt=8, seed=s, dt=dt).samples[i]
-           for dt, s, i in SOC_PICKS]
-    b = synthgen.Batch(smp, name="fisher_kpp").pack()
-    res = gpu_project(b, snap.Options(flags=snap.FLAG_SOC))
-    st = res["stats"]
-    assert (st["status"] == 0).all(), st["status"]
-    u_o, _, _ = project_batch(b)
-    for s, o in zip(b.samples, b.var_off):
-        assert rel_err(res["u_np"][o:o + s.n], u_o[o:o + s.n]) <= 1e-10
+    b = _batch()
+    res = gpu_project(b, snap.Options(flags=snap.FLAG_SOC, max_newton=60))
+    check_samples(b, res, range(len(b)), 1e-10, 1e-8)
