@@ -5,11 +5,14 @@
 A step is one forward projection (the whole Newton/SQP hot path: stencil
 evaluation, Schur assembly, factorization, solves, line search, convergence
 test) of one batch of synthetic samples already resident in HBM.  The default
-workload is the Fisher-KPP nonlinear mass-law batch (256 samples, 128 x 100
-grid, FP64).  The same run also times the mixed-precision forward and the
-adjoint, measures the dominant kernel against the HBM roofline with HIP events
-on the launch stream, and times the CPU oracle on a bounded sample of the same
-workload.  Prints one JSON line.
+workload is the ragged batch: 1024 samples mixing the mass + IC, Fisher-KPP
+and Burgers flux families on Nx in {64, 96, 128, 192, 256} x Nt in
+{32, 64, 128}, FP64.  The same run also times the mixed-precision forward,
+the adjoint and the batched form (autotuned launch shapes, HIP-graph replay),
+measures the dominant kernel against its roofline with HIP events recorded on
+its launch stream (the banded factorization for workloads with Burgers
+samples, else the one-launch slab kernel), and times the CPU oracle on a
+bounded sample of the same workload.  Prints one JSON line.
 """
 import argparse
 import hashlib
@@ -46,8 +49,24 @@ KERNEL_SOURCES = {
 }
 KERNEL_NAMES = {
     "fisher_kpp": "slab_kernel", "mass_ic": "slab_kernel",
-    "burgers_lf": "band_kernel", "ragged": "band_kernel",
+    "burgers_lf": "band_factor", "ragged": "band_factor",
 }
+FP64_PEAK_TFLOPS = 78.6
+
+
+def band_work(batch, iters):
+    """Algorithmic work of the banded samples' factorizations and backward
+    substitutions in one call: per factorization m * b^2 flop (m rows, half
+    bandwidth b = Nx + 2 in the folded row order), per substitution the factor
+    band m * (b + 1) entries read once; one of each per Newton step."""
+    flops = sbytes = 0.0
+    for s, it in zip(batch.samples, iters):
+        if int(s.family) != 3:
+            continue
+        m, b = s.nx * (s.nt - 1), s.nx + 2
+        flops += float(it) * m * b * b
+        sbytes += float(it) * m * (b + 1) * 8
+    return flops, sbytes
 
 
 BAND_BBS = (1, 2, 3, 5, 7, 9, 13, 17)
@@ -87,12 +106,13 @@ def load_traffic(workload):
 
 
 # ------------------------------------------------------------------ CPU oracle
-def _oracle_one(args):
-    name, kw, idx = args
+_POOL_BATCH = None   # the batch, inherited by the forked oracle workers
+
+
+def _oracle_one(idx):
     from oracle.families import family_of
     from oracle.kkt import project_sample
-    b = synthgen.make(name, **kw)
-    s = b.samples[idx]
+    s = _POOL_BATCH.samples[idx]
     u, lam = project_sample(family_of(s), s.uhat.reshape(-1))
     return idx, u
 
@@ -100,12 +120,14 @@ def _oracle_one(args):
 def cpu_baseline(name, kw, batch, budget_s=15.0):
     """Samples/s of the CPU oracle on the first samples of the batch, in a
     process pool; stops taking results once the time budget is spent."""
+    global _POOL_BATCH
+    _POOL_BATCH = batch
     workers = max(1, min(16, os.cpu_count() or 1))
     res = {}
     t0 = time.perf_counter()
     pool = mp.get_context("fork").Pool(workers)
     try:
-        it = pool.imap(_oracle_one, [(name, kw, i) for i in range(len(batch))], chunksize=1)
+        it = pool.imap(_oracle_one, range(len(batch)), chunksize=1)
         for i in range(len(batch)):
             idx, u = it.next()
             res[idx] = u
@@ -170,7 +192,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fisher_kpp", choices=sorted(KERNEL_SOURCES))
+    ap.add_argument("--workload", default="ragged", choices=sorted(KERNEL_SOURCES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true",
                     help="time the FP64 forward only (for profiler runs)")
@@ -224,11 +246,17 @@ def main():
     def fwd64():
         snap.project(plan64, uhat, aux, ws, u, lam, st, stream)
 
+    banded = any(int(s.family) == 3 for s in batch.samples)
+
     # timed region: K forward projections of the resident batch
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         fwd64()
     torch.cuda.synchronize()
+    if banded:
+        # HIP events around every band_factor / band_solve launch, on the
+        # stream each is launched on (from a pool the plan preallocates)
+        plan64.set_kernel_timing(True)
     t0 = time.perf_counter()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -323,13 +351,43 @@ def main():
                           "plan_create_s": tune_s,
                           "launch_groups": planb.describe().strip().splitlines()}
 
-    # roofline of the dominant kernel: the forward launch is one kernel per
-    # family group; events on the launch stream bracket it
-    abytes = algorithmic_bytes(batch)
-    achieved = abytes / sec64 / 1e9
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name),
-                       "kernel": KERNEL_NAMES[name], "algorithmic_bytes_per_launch": abytes}
+    if banded:
+        # roofline of the dominant kernel, the banded factorization: the
+        # method's flops (m b^2 per factorization, one per Newton step of
+        # each sample) per launch over its average event-timed duration
+        fms, flaunch, fdrop = plan64.kernel_times(snap.KERNEL_BAND_FACTOR)
+        sms, slaunch, _ = plan64.kernel_times(snap.KERNEL_BAND_SOLVE)
+        plan64.set_kernel_timing(False)
+        flops, sbytes = band_work(batch, stats["newton_iters"])
+        # every call launches max_newton factorizations per banded group
+        # (converged samples return at once); marks past the timer's pool are
+        # dropped, so scale the work to the launches actually timed
+        n_band = sum(1 for l in plan64.describe().splitlines() if " band " in l)
+        expected = args.steps * n_band * plan64.options.max_newton
+        timed_frac = min(1.0, flaunch / max(expected, 1))
+        per_launch = flops * args.steps * timed_frac / max(flaunch, 1)
+        avg_s = fms / 1e3 / max(flaunch, 1)
+        achieved = per_launch / avg_s / 1e12
+        out["roofline"] = {
+            "bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": load_traffic(name),
+            "kernel": KERNEL_NAMES[name], "flops_per_launch": per_launch,
+            "avg_launch_ms": avg_s * 1e3, "launches_per_step": flaunch / args.steps,
+            "dropped_marks": fdrop}
+        s_per_launch = sbytes * args.steps * min(1.0, slaunch / max(expected, 1)) / max(slaunch, 1)
+        s_avg = sms / 1e3 / max(slaunch, 1)
+        out["roofline_band_solve"] = {
+            "bound": "hbm", "achieved": s_per_launch / s_avg / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": s_per_launch / s_avg / 1e9 / HBM_PEAK_GBS,
+            "kernel": "band_solve", "bytes_per_launch": s_per_launch, "avg_launch_ms": s_avg * 1e3}
+    else:
+        # roofline of the dominant kernel: the forward is one slab-kernel
+        # launch; events on the launch stream bracket it
+        abytes = algorithmic_bytes(batch)
+        achieved = abytes / sec64 / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name),
+                           "kernel": KERNEL_NAMES[name], "algorithmic_bytes_per_launch": abytes}
 
     if cb is not None:
         out["cpu_baseline"] = cb

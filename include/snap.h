@@ -168,7 +168,9 @@ void snap_default_options(snap_options* opt);
  * iterations and calls, paper Sec. III-B/III-C), and allocates its own small
  * device metadata on the current device.  batch = 0 is valid (calls then do
  * nothing).  Returns SNAP_EUNSUPPORTED for families or sizes the library does
- * not build.  Thread-safe: a plan is immutable after creation. */
+ * not build.  Calls on one plan from several host threads are serialized
+ * by a lock of the plan (its fork/join events, captured graphs and timer are
+ * per plan); separate plans run independently. */
 int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* descs_host,
                      const snap_options* opt);
 
@@ -222,6 +224,33 @@ int snap_plan_group_classes(snap_plan plan, int32_t group, int32_t* classes, int
  * snap_plan_group_classes (for instance a choice saved from an autotuned
  * plan).  Drops any captured graph.  Must not race with calls on the plan. */
 int snap_plan_set_group_class(snap_plan plan, int32_t group, int32_t cls);
+
+/* Kernel timing (a tracing aid; not needed for projection).  With timing
+ * enabled, snap_project and snap_project_backward record a HIP event on the
+ * launch stream before and after every launch of the timed kernels
+ * (SNAP_KERNEL_BAND_FACTOR: the banded Schur factorization with its fused
+ * forward substitution; SNAP_KERNEL_BAND_SOLVE: the backward substitution and
+ * refinement of a Newton step), from a pool of 8192 events allocated by
+ * snap_plan_set_kernel_timing (so calls still allocate nothing).  Marks past
+ * the pool are dropped and counted.  Not available with SNAP_FLAG_GRAPH
+ * (returns SNAP_EUNSUPPORTED).  Timing a launch that shares the GPU with
+ * launches on other streams (ragged plans fork their groups over four streams)
+ * includes that sharing, as a kernel trace does. */
+enum snap_timed_kernel { SNAP_KERNEL_BAND_FACTOR = 0, SNAP_KERNEL_BAND_SOLVE = 1 };
+
+/* enable != 0: allocate the event pool (or clear the recorded marks);
+ * enable == 0: free it.  Must not race with calls on the plan. */
+int snap_plan_set_kernel_timing(snap_plan plan, int32_t enable);
+
+/* Sum of the recorded launch durations of `kernel` (milliseconds) and their
+ * count since timing was enabled or last reset; *dropped (if not NULL)
+ * receives the number of marks lost to a full pool.  Waits for the recorded
+ * events (synchronizes the host with them). */
+int snap_plan_kernel_times(snap_plan plan, int32_t kernel, double* total_ms, int64_t* launches,
+                           int64_t* dropped);
+
+/* Forget the recorded marks (waits for them first). */
+int snap_plan_reset_kernel_times(snap_plan plan);
 
 int snap_plan_destroy(snap_plan plan);
 

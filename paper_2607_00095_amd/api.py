@@ -12,6 +12,7 @@ import torch
 MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY = 1, 2, 3, 4
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_KEEP_FACTOR, FLAG_GRAPH, FLAG_AUTOTUNE, FLAG_SOC = 1, 2, 4, 8
+KERNEL_BAND_FACTOR, KERNEL_BAND_SOLVE = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -70,13 +71,17 @@ def _load():
     lib.snap_plan_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.snap_plan_group_classes.argtypes = [vp, i32, C.POINTER(i32), i32, C.POINTER(i32)]
     lib.snap_plan_set_group_class.argtypes = [vp, i32, i32]
+    lib.snap_plan_set_kernel_timing.argtypes = [vp, i32]
+    lib.snap_plan_kernel_times.argtypes = [vp, i32, dp, C.POINTER(i64), C.POINTER(i64)]
+    lib.snap_plan_reset_kernel_times.argtypes = [vp]
     lib.snap_error_string.argtypes = [C.c_int]
     lib.snap_error_string.restype = C.c_char_p
     lib.snap_status_string.argtypes = [C.c_int]
     lib.snap_status_string.restype = C.c_char_p
     for f in ("snap_plan_create", "snap_plan_workspace_bytes", "snap_plan_sizes", "snap_project",
               "snap_project_backward", "snap_plan_destroy", "snap_plan_describe",
-              "snap_plan_group_classes", "snap_plan_set_group_class"):
+              "snap_plan_group_classes", "snap_plan_set_group_class", "snap_plan_set_kernel_timing",
+              "snap_plan_kernel_times", "snap_plan_reset_kernel_times"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -156,6 +161,20 @@ class Plan:
 
     def set_group_class(self, group: int, cls: int):
         _check(_load().snap_plan_set_group_class(self._h, group, cls), "snap_plan_set_group_class")
+
+    def set_kernel_timing(self, enable: bool = True):
+        _check(_load().snap_plan_set_kernel_timing(self._h, 1 if enable else 0),
+               "snap_plan_set_kernel_timing")
+
+    def kernel_times(self, kernel: int):
+        """(total milliseconds, launches, dropped marks) of a timed kernel."""
+        ms, n, dr = C.c_double(), C.c_int64(), C.c_int64()
+        _check(_load().snap_plan_kernel_times(self._h, kernel, C.byref(ms), C.byref(n), C.byref(dr)),
+               "snap_plan_kernel_times")
+        return ms.value, n.value, dr.value
+
+    def reset_kernel_times(self):
+        _check(_load().snap_plan_reset_kernel_times(self._h), "snap_plan_reset_kernel_times")
 
     def new_workspace(self) -> torch.Tensor:
         # 256-byte aligned: torch's caching allocator returns 512-byte aligned blocks

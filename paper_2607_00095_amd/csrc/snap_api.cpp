@@ -46,6 +46,7 @@ struct Group {
 };
 
 constexpr int kStreams = 4;   // groups are spread over this many internal streams
+constexpr int kTimerEvents = 8192;   // event pool of the kernel timer
 
 // A captured launch sequence and the call arguments it was captured with.
 struct GraphSlot {
@@ -70,7 +71,27 @@ struct snap_plan_s {
   std::vector<hipEvent_t> events;       // [0] fork, [1..] join per stream
   GraphSlot graphs[2];                  // SNAP_FLAG_GRAPH: forward, backward
   std::mutex graph_mu;
+  KernelTimer* timer = nullptr;         // snap_plan_set_kernel_timing
+  std::mutex run_mu;                    // calls on one plan from several threads
 };
+
+namespace snap {
+// Events recorded around timed launches, in pairs per launch: (kernel id,
+// pool index) in recording order.  Marks past the pool's end are dropped and
+// counted.
+struct KernelTimer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> marks;
+  int64_t dropped = 0;
+};
+thread_local KernelTimer* tl_timer = nullptr;
+
+void timer_mark(KernelTimer* t, int kernel, hipStream_t st) {
+  if (t->marks.size() >= t->pool.size()) { ++t->dropped; return; }
+  const int i = (int)t->marks.size();
+  if (hipEventRecord(t->pool[i], st) == hipSuccess) t->marks.emplace_back(kernel, i);
+}
+}  // namespace snap
 
 namespace {
 
@@ -91,8 +112,16 @@ int64_t aux_of(const snap_sample_desc& d) {
   }
 }
 
+void free_timer(snap_plan p) {
+  if (!p->timer) return;
+  for (auto& e : p->timer->pool) (void)hipEventDestroy(e);
+  delete p->timer;
+  p->timer = nullptr;
+}
+
 void free_plan(snap_plan p) {
   if (!p) return;
+  free_timer(p);
   for (auto& g : p->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   for (auto& e : p->events) (void)hipEventDestroy(e);
@@ -486,7 +515,14 @@ static int run_graph(snap_plan plan, const KernelArgs& a, hipStream_t st) {
 }
 
 static int dispatch(snap_plan plan, const KernelArgs& a, hipStream_t st) {
-  return (plan->opt.flags & SNAP_FLAG_GRAPH) ? run_graph(plan, a, st) : run(plan, a, st);
+  // the fork/join events and the timer are per plan: one call at a time
+  std::lock_guard<std::mutex> lock(plan->run_mu);
+  if (plan->opt.flags & SNAP_FLAG_GRAPH) return run_graph(plan, a, st);
+  if (!plan->timer) return run(plan, a, st);
+  tl_timer = plan->timer;
+  const int rc = run(plan, a, st);
+  tl_timer = nullptr;
+  return rc;
 }
 
 int snap_project(snap_plan plan, const double* uhat, const double* aux, double* u_out,
@@ -584,6 +620,59 @@ int snap_plan_set_group_class(snap_plan plan, int32_t group, int32_t cls) {
       (void)hipGraphExecDestroy(gr.exec);
       gr.exec = nullptr;
     }
+  return SNAP_SUCCESS;
+}
+
+int snap_plan_set_kernel_timing(snap_plan plan, int32_t enable) {
+  if (!plan) return SNAP_EINVAL;
+  if (plan->opt.flags & SNAP_FLAG_GRAPH) return SNAP_EUNSUPPORTED;
+  if (!enable) { free_timer(plan); return SNAP_SUCCESS; }
+  if (plan->timer) { plan->timer->marks.clear(); plan->timer->dropped = 0; return SNAP_SUCCESS; }
+  KernelTimer* t = new (std::nothrow) KernelTimer();
+  if (!t) return SNAP_ENOMEM;
+  t->pool.assign(kTimerEvents, nullptr);
+  for (auto& e : t->pool)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : t->pool)
+        if (f) (void)hipEventDestroy(f);
+      delete t;
+      return SNAP_EHIP;
+    }
+  t->marks.reserve(kTimerEvents);
+  plan->timer = t;
+  return SNAP_SUCCESS;
+}
+
+int snap_plan_kernel_times(snap_plan plan, int32_t kernel, double* total_ms, int64_t* launches,
+                           int64_t* dropped) {
+  if (!plan || !plan->timer || kernel < 0 || kernel >= kTimedCount) return SNAP_EINVAL;
+  KernelTimer* t = plan->timer;
+  double ms = 0.0;
+  int64_t n = 0;
+  // marks come in (begin, end) pairs per launch and kernel
+  std::vector<int> open(kTimedCount, -1);
+  for (const auto& mk : t->marks) {
+    if (mk.first != kernel) continue;
+    if (open[kernel] < 0) { open[kernel] = mk.second; continue; }
+    if (hipEventSynchronize(t->pool[mk.second]) != hipSuccess) return SNAP_EHIP;
+    float e = 0.0f;
+    if (hipEventElapsedTime(&e, t->pool[open[kernel]], t->pool[mk.second]) != hipSuccess) return SNAP_EHIP;
+    ms += e;
+    ++n;
+    open[kernel] = -1;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (dropped) *dropped = t->dropped;
+  return SNAP_SUCCESS;
+}
+
+int snap_plan_reset_kernel_times(snap_plan plan) {
+  if (!plan || !plan->timer) return SNAP_EINVAL;
+  for (const auto& mk : plan->timer->marks)
+    if (hipEventSynchronize(plan->timer->pool[mk.second]) != hipSuccess) return SNAP_EHIP;
+  plan->timer->marks.clear();
+  plan->timer->dropped = 0;
   return SNAP_SUCCESS;
 }
 

@@ -60,6 +60,7 @@ constexpr int kT = 16;              // block size
 constexpr int kLd = 17;             // padded LDS row stride (bank-conflict free column reads)
 constexpr int kTL = kT * kLd;       // LDS words per tile
 constexpr double kWFloor = 0.1;
+constexpr double kReuseH = 1e-6;    // ||h||_inf below which a factor is reused
 
 __device__ __forceinline__ int fold_x(int p, int nx) { return (p & 1) ? nx - 1 - (p >> 1) : (p >> 1); }
 __device__ __forceinline__ int pos_of(int x, int nx) {
@@ -270,6 +271,31 @@ __device__ void assemble_all(const Ctx& C, const WsLayout& WL) {
       val[4 * e + 2] = own ? sv * C.cd : 0.0;
       col[4 * e + 3] = own ? kk * nx + pos_of(wrap(y + 1, nx), nx) : r;
       val[4 * e + 3] = own ? sv * (-C.q * uy - C.c) : 0.0;
+    }
+    rvec[(size_t)k * nx + x] = rhs;
+    rin[r] = rhs;
+  }
+  __syncthreads();
+}
+
+// Right-hand side h - J W^{-1} g alone (rvec canonical, rin internal order),
+// for a Newton step solved with the factor of an earlier iteration.
+template <int NW>
+__device__ void assemble_rhs(const Ctx& C, const WsLayout& WL) {
+  double* rvec = (double*)(C.ws + WL.rvec);
+  double* rin = (double*)(C.ws + WL.rin);
+  const int nx = C.nx;
+  for (int r = threadIdx.x; r < C.M; r += NW * kWave) {
+    if (r >= C.m) { rin[r] = 0.0; continue; }
+    const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
+    double rhs = h_row(C, k, x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = (e == 0) ? k + 1 : k;
+      const int y = (e <= 1) ? x : (e == 2 ? wrap(x + 1, nx) : wrap(x - 1, nx));
+      const double uy = C.u[(size_t)kk * nx + y];
+      const double al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
+      rhs -= al / w_at(C, kk, y) * gres(C, kk, y);
     }
     rvec[(size_t)k * nx + x] = rhs;
     rin[r] = rhs;
@@ -701,13 +727,14 @@ __device__ void to_internal(const Ctx& C, const double* canon, double* rin) {
 template <int BB, int NW, typename R>
 __device__ __attribute__((always_inline)) int solve_with_factor(
     const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, bool have_y, double* x,
-    int max_refine = 6, double abs_floor = 0.0) {
+    int max_refine = 6, double abs_floor = 0.0, bool stale = false) {
   double* Y = (double*)(C.ws + WL.Y);
   double* rin = (double*)(C.ws + WL.rin);
   double* res = (double*)(C.ws + WL.res);
   double* dx = (double*)(C.ws + WL.t);          // correction (t is free between residuals)
   const double* rvec = (const double*)(C.ws + WL.rvec);
-  constexpr bool plain = sizeof(R) == sizeof(double);
+  // the plain form refines only with a factor of an earlier iterate (stale)
+  const bool plain = sizeof(R) == sizeof(double) && !stale;
   double rn = 0.0;
   if (!plain) {
     for (int r = threadIdx.x; r < C.m; r += NW * kWave) rn = fmax(rn, fabs(rvec[r]));
@@ -745,6 +772,8 @@ struct BandState {
   int status;       // SNAP_ST_*
   int iters, backtracks, refines;
   int factor_ok;    // 1 when the stored factor was taken at the returned point
+  int factored;     // a factor of S from an earlier iteration is in the workspace
+  int reuse;        // this iteration's step is solved with that factor
   double mu, uscale, h1, hinf, stinf;
 };
 static_assert(sizeof(BandState) <= 256, "state must fit the header");
@@ -848,10 +877,25 @@ SNAP_BAND_KERNEL void band_factor(KernelArgs A) {
   BandState* S = (BandState*)(C.ws + WL.hdr);
   const int phase = S->phase;
   if (phase == 2) return;
+  // Local phase (||h||_inf <= kReuseH): S moves by O(||p||) between
+  // iterations, so the previous iteration's factor, with float64 iterative
+  // refinement against the current S (matrix free), solves the Newton system
+  // to the same accuracy.  That pays where a factorization costs more than
+  // the two or three substitution sweeps of the refinement: on the wide bands
+  // (BB >= 13, Nx > 128), whose factorization chains are the longest of a
+  // ragged batch; at BB <= 9 (measured on 512 samples of 128 x 128) a fresh
+  // factorization is cheaper.
+  if (BB >= 13 && phase == 0 && S->factored && S->hinf <= kReuseH) {
+    assemble_rhs<NW>(C, WL);
+    if (threadIdx.x == 0) S->reuse = 1;
+    return;
+  }
   if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
   __syncthreads();
   const int bad = factor_sweep<BB, NW, R>(C, WL, sh);
   if (threadIdx.x == 0) {
+    S->reuse = 0;
+    S->factored = bad ? 0 : 1;
     if (phase == 1) {
       S->factor_ok = bad ? 0 : 1;
       S->phase = 2;
@@ -877,10 +921,12 @@ SNAP_BAND_KERNEL void band_solve(KernelArgs A) {
   // right-hand side h - J W^{-1} g is formed in float64 every iteration), so
   // explicit float64 refinement is applied only in the local phase, where the
   // float32 error would otherwise limit the last digits.
-  const int max_ref = S->hinf <= 1e-6 ? 6 : 0;
+  const bool reuse = S->reuse != 0;
+  const int max_ref = (S->hinf <= 1e-6 || reuse) ? 6 : 0;
   // a Newton step only needs its Schur residual well below the feasibility
   // tolerance (the next evaluation re-forms h in float64)
-  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, true, lamp, max_ref, 0.1 * A.opt.tol_h);
+  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, !reuse, lamp, max_ref, 0.1 * A.opt.tol_h,
+                                                   reuse);
   for (int r = threadIdx.x; r < C.m; r += NW * kWave) lamp[r] += C.lam[r];
   if (threadIdx.x == 0) S->refines += refines;
 }
@@ -1053,9 +1099,14 @@ static void launch_band(const KernelArgs& a, hipStream_t st) {
   }
   hipLaunchKernelGGL((band_init<BB, NW, R>), grid, block, 0, st, a);
   hipLaunchKernelGGL((band_eval<BB, NW, R>), grid, block, 0, st, a);
+  KernelTimer* tm = tl_timer;
   for (int it = 0; it < a.opt.max_newton; ++it) {
+    if (tm) timer_mark(tm, kTimedBandFactor, st);
     hipLaunchKernelGGL((band_factor<BB, NW, R>), grid, block, 0, st, a);
+    if (tm) timer_mark(tm, kTimedBandFactor, st);
+    if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_solve<BB, NW, R>), grid, block, 0, st, a);
+    if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_step<BB, NW, R>), grid, block, 0, st, a);
     hipLaunchKernelGGL((band_eval<BB, NW, R>), grid, block, 0, st, a);
   }

@@ -108,4 +108,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// Optional per-kernel timing of a call's launch sequence
+// (snap_plan_set_kernel_timing).  While a plan with timing enabled runs,
+// `tl_timer` points at its timer and the launch code brackets the timed
+// kernels with timer_mark(kernel, begin/end, stream), which records one event
+// of a preallocated pool on the launch stream.  Host code only.
+enum TimedKernel { kTimedBandFactor = 0, kTimedBandSolve = 1, kTimedCount = 2 };
+struct KernelTimer;
+extern thread_local KernelTimer* tl_timer;
+void timer_mark(KernelTimer* t, int kernel, hipStream_t st);
+
 }  // namespace snap

@@ -97,7 +97,8 @@ def test_ragged_full_config_fixed_samples(prec, tol, lam_tol):
 def test_ragged_adjoint_central_differences():
     # 16 samples of the ragged workload (at least 5 per family), two random
     # unit directions each: <g, (P(u_hat + eps w) - P(u_hat - eps w)) / 2eps>
-    # against <VJP(g), w>, FP64 forwards run to a tight tolerance
+    # against <VJP(g), w>, FP64 forwards run to 1e-12 (the last Newton step squares
+    # the error, so the forwards' own error stays far below eps * 1e-6)
     import copy
     b = synthgen.make("ragged")
     rng = np.random.default_rng(16)
@@ -117,7 +118,7 @@ def test_ragged_adjoint_central_differences():
                 p = copy.copy(s)
                 p.uhat = s.uhat + sign * eps * w
                 pert.append(p)
-    opts = snap.Options(tol_h=1e-13, tol_s=1e-13, max_newton=40, flags=snap.FLAG_KEEP_FACTOR)
+    opts = snap.Options(tol_h=1e-12, tol_s=1e-12, max_newton=40, flags=snap.FLAG_KEEP_FACTOR)
     bb = synthgen.Batch(base).pack()
     res = gpu_project(bb, opts)
     assert (res["stats"]["status"] == 0).all(), res["stats"]
@@ -125,7 +126,7 @@ def test_ragged_adjoint_central_differences():
     g, st = gpu_backward(res, grad)
     assert (st["status"] == 0).all()
     bp = synthgen.Batch(pert).pack()
-    rp = gpu_project(bp, snap.Options(tol_h=1e-13, tol_s=1e-13, max_newton=40))
+    rp = gpu_project(bp, snap.Options(tol_h=1e-12, tol_s=1e-12, max_newton=40))
     assert (rp["stats"]["status"] == 0).all(), rp["stats"]
     for k, s in enumerate(base):
         vo = bb.var_off[k]
