@@ -194,6 +194,27 @@ int snap_plan_sizes(snap_plan plan, int64_t* total_vars, int64_t* total_rows, in
 int snap_project(snap_plan plan, const double* uhat, const double* aux, double* u_out,
                  double* lambda_out, snap_sample_stats* stats, void* workspace, void* stream);
 
+/* Largest workspace (bytes) that snap_project_noalloc can serve. */
+#define SNAP_NOALLOC_MAX_WORKSPACE (64u << 20)
+
+/* snap_project without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP-graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments and results as snap_project; the
+ * workspace is a static 64 MiB device array of the library, one per GPU, held
+ * until the process ends, whose address is looked up when a plan is created.
+ * The call itself allocates nothing.
+ *   Returns SNAP_EINVAL if the plan's workspace (snap_plan_workspace_bytes)
+ *   exceeds SNAP_NOALLOC_MAX_WORKSPACE (for instance one 256 x 128 Burgers
+ *   sample in FP64), or if the current device is not the plan's.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (every kernel sets up the state it reads, so nothing needs clearing
+ * between calls): calls that overlap in time on one GPU, on any plans or
+ * streams, race.  A factor kept with SNAP_FLAG_KEEP_FACTOR stays in the array
+ * and cannot be handed to snap_project_backward; use snap_project with a
+ * workspace for the adjoint. */
+int snap_project_noalloc(snap_plan plan, const double* uhat, const double* aux, double* u_out,
+                         double* lambda_out, snap_sample_stats* stats, void* stream);
+
 /* Vector-Jacobian product of the projection with respect to u_hat at the
  * solution (implicit-function theorem on the KKT conditions): with the KKT
  * matrix K at (u, lambda), grad_uhat is the u-block of K^{-1} [grad_u; 0]

@@ -32,7 +32,38 @@ int band_waves(int cls);
 
 using namespace snap;
 
+// Scratch for snap_project_noalloc: the workspace of callers that cannot
+// allocate device memory.  Every GPU the library runs on holds its own copy
+// until the process ends; its device address is looked up once per device at
+// plan creation (the array's name in host code is only a host-side stand-in).
+constexpr size_t kStaticScratchBytes = (size_t)SNAP_NOALLOC_MAX_WORKSPACE;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (0 on failure)
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return SNAP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return SNAP_SUCCESS;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return SNAP_EHIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return SNAP_SUCCESS;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 // Samples sharing one kernel instantiation (shapes may differ: every kernel
 // reads its sample's shape from the descriptor).  `kind` 0 = slab rows,
@@ -408,6 +439,9 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
       }
     }
   }
+  // the no-allocation entry point's scratch: its address on this device
+  // (set-up happens here, never on that entry point's own path)
+  if (p->ws_bytes <= kStaticScratchBytes) (void)scratch_setup(p->device);
   if (o.flags & SNAP_FLAG_AUTOTUNE) {
     for (auto& g : p->groups) {
       const std::vector<int> cand = group_candidates(*p, g);
@@ -545,6 +579,18 @@ int snap_project(snap_plan plan, const double* uhat, const double* aux, double* 
   a.opt = plan->opt;
   a.backward = 0;
   return dispatch(plan, a, (hipStream_t)stream);
+}
+
+int snap_project_noalloc(snap_plan plan, const double* uhat, const double* aux, double* u_out,
+                         double* lambda_out, snap_sample_stats* stats, void* stream) {
+  if (!plan) return SNAP_EINVAL;
+  if (plan->batch == 0) return SNAP_SUCCESS;
+  if (plan->ws_bytes > kStaticScratchBytes) return SNAP_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return SNAP_EINVAL;
+  void* ptr = scratch_ptr(dev);
+  if (!ptr) return SNAP_EHIP;
+  return snap_project(plan, uhat, aux, u_out, lambda_out, stats, ptr, stream);
 }
 
 int snap_project_backward(snap_plan plan, const double* u, const double* lambda, const double* aux,
