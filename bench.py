@@ -46,10 +46,11 @@ KERNEL_SOURCES = {
     "mass_ic": "paper_2607_00095_amd/csrc/snap_slab.hip",
     "burgers_lf": "paper_2607_00095_amd/csrc/snap_band.hip",
     "ragged": "paper_2607_00095_amd/csrc/snap_band.hip",
+    "diff2d_energy": "paper_2607_00095_amd/csrc/snap_spec.hip",
 }
 KERNEL_NAMES = {
     "fisher_kpp": "slab_kernel", "mass_ic": "slab_kernel",
-    "burgers_lf": "band_factor", "ragged": "band_factor",
+    "burgers_lf": "band_factor", "ragged": "band_factor", "diff2d_energy": "spec_kernel",
 }
 FP64_PEAK_TFLOPS = 78.6
 
@@ -380,6 +381,15 @@ def main():
             "bound": "hbm", "achieved": s_per_launch / s_avg / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": s_per_launch / s_avg / 1e9 / HBM_PEAK_GBS,
             "kernel": "band_solve", "bytes_per_launch": s_per_launch, "avg_launch_ms": s_avg * 1e3}
+    elif name == "diff2d_energy":
+        # one spectral-kernel launch per call: per Newton iteration a sample
+        # must read u and u_hat and write u and lambda (float64)
+        abytes = sum(max(int(it), 1) * 8 * (3 * s.n + s.m)
+                     for s, it in zip(batch.samples, stats["newton_iters"]))
+        achieved = abytes / sec64 / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name),
+                           "kernel": KERNEL_NAMES[name], "algorithmic_bytes_per_launch": abytes}
     else:
         # roofline of the dominant kernel: the forward is one slab-kernel
         # launch; events on the launch stream bracket it

@@ -53,7 +53,17 @@ extern "C" {
  *                   f(u_{i-1}^k)) - c(u_{i+1}^k - 2u_i^k + u_{i-1}^k), f = u^2/2,
  *                   q = dt/(2dx), c = p1*dt/(2dx) + p0*dt/dx^2.
  *                   p0 = nu, p1 = alpha (flux speed).  No aux.
- * SNAP_DIFF2D_ENERGY  reserved (2D diffusion + per-frame energy); not built.
+ * SNAP_DIFF2D_ENERGY  implicit 2D diffusion residuals plus one energy row per
+ *                   frame (Appendix A Navier-Stokes constraint set: local PDE
+ *                   residuals and a global quadratic invariant), periodic
+ *                   Nx x Ny grid (Nx = Ny in {16, 32, 48, 64}), 1 <= Nt <= 16.
+ *                   Rows, canonical order: (k, y, x) for k = 0..Nt-2,
+ *                   u(k+1) - u(k) - dt*p0*Lap5 u(k+1) with the periodic
+ *                   5-point Laplacian of spacing dx; then, for t = 0..Nt-1,
+ *                   sum_{y,x} u(t)^2 - E_t.  p0 = kappa.  aux = [E(Nt)].
+ *                   Solved in the orthonormal real Fourier basis of each
+ *                   frame; PREC_MIXED runs the same FP64 arithmetic (the
+ *                   family has no band factorization to lower).
  */
 enum snap_family {
   SNAP_MASS_IC = 1,
@@ -124,7 +134,13 @@ enum snap_sample_status {
   SNAP_ST_MAX_ITER = 1,       /* max_newton iterations without meeting the tolerances */
   SNAP_ST_LS_FAIL = 2,        /* line search found no decrease of the merit */
   SNAP_ST_NONFINITE = 3,      /* NaN/Inf in input or iterates */
-  SNAP_ST_SINGULAR_PIVOT = 4  /* non-positive pivot in the Schur factorization */
+  SNAP_ST_SINGULAR_PIVOT = 4, /* non-positive pivot in the Schur factorization (2D
+                                 family: a mode's reduced Hessian or the energy
+                                 border is not positive definite) */
+  SNAP_ST_HESSIAN_FLOOR = 5   /* adjoint only: the Lagrangian Hessian at (u*, lam*)
+                                 has entries below the 0.1 floor the Newton steps
+                                 use, so the gradient was formed with the floored
+                                 W and is not the implicit-function derivative */
 };
 
 /* One sample.  Offsets are element offsets into the packed arrays. */

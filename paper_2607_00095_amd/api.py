@@ -40,7 +40,7 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("newton_iters", "<i4"), ("ls_backtra
                         ("refine_steps", "<i4"), ("h_inf", "<f8"), ("stat_inf", "<f8")])
 
 _STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed", 3: "nonfinite",
-           4: "singular_pivot"}
+           4: "singular_pivot", 5: "hessian_floor"}
 
 
 def status_name(code: int) -> str:

@@ -28,6 +28,9 @@ int slab_variants(int nx, int nt, int* out, int cap);
 int band_variants(int cls, int* out, int cap);
 int slab_waves(int cls);
 int band_waves(int cls);
+bool spec_supported(int nx, int ny, int nt);
+size_t spec_workspace_bytes(int nx, int nt);
+int spec_launch(const KernelArgs& a, hipStream_t st);
 }  // namespace snap
 
 using namespace snap;
@@ -67,7 +70,7 @@ void* scratch_ptr(int device) {
 
 // Samples sharing one kernel instantiation (shapes may differ: every kernel
 // reads its sample's shape from the descriptor).  `kind` 0 = slab rows,
-// 1 = banded; `cls` = instantiation index; ids sorted by decreasing cost so
+// 1 = banded, 2 = spectral (2D diffusion + energy); `cls` = instantiation index; ids sorted by decreasing cost so
 // the longest samples start first.
 struct Group {
   int kind, cls;
@@ -95,6 +98,7 @@ struct snap_plan_s {
   std::vector<Group> groups;
   std::vector<int64_t> ws_off;   // per-sample byte offsets
   int64_t* d_ws_off = nullptr;
+  double* d_tab = nullptr;              // Fourier basis tables (2D family)
   size_t ws_bytes = 0;
   int64_t total_vars = 0, total_rows = 0, total_aux = 0;
   int device = 0;
@@ -131,6 +135,7 @@ int64_t rows_of(const snap_sample_desc& d) {
     case SNAP_MASS_IC:
     case SNAP_FISHER_KPP: return (int64_t)d.nx + d.nt - 1;
     case SNAP_BURGERS_LF: return (int64_t)d.nx * (d.nt - 1);
+    case SNAP_DIFF2D_ENERGY: return (int64_t)d.nx * d.ny * (d.nt - 1) + d.nt;
     default: return -1;
   }
 }
@@ -139,6 +144,7 @@ int64_t aux_of(const snap_sample_desc& d) {
   switch (d.family) {
     case SNAP_MASS_IC: return d.nx + 1;
     case SNAP_FISHER_KPP: return d.nx;
+    case SNAP_DIFF2D_ENERGY: return d.nt;
     default: return 0;
   }
 }
@@ -161,6 +167,7 @@ void free_plan(snap_plan p) {
     if (g.d_ids) (void)hipFree(g.d_ids);
   if (p->d_descs) (void)hipFree(p->d_descs);
   if (p->d_ws_off) (void)hipFree(p->d_ws_off);
+  if (p->d_tab) (void)hipFree(p->d_tab);
   delete p;
 }
 
@@ -181,7 +188,8 @@ std::vector<int> group_candidates(const snap_plan_s& p, const Group& g) {
   for (size_t i = 0; i < g.ids.size(); ++i) {
     const snap_sample_desc& d = p.descs[g.ids[i]];
     int v[8];
-    const int n = g.kind == 0 ? slab_variants(d.nx, d.nt, v, 8) : band_variants(g.cls, v, 8);
+    const int n = g.kind == 0 ? slab_variants(d.nx, d.nt, v, 8)
+                  : g.kind == 1 ? band_variants(g.cls, v, 8) : (v[0] = 0, 1);
     std::vector<int> mine(v, v + n);
     if (i == 0) {
       cand = mine;
@@ -363,7 +371,8 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
   size_t ws = 0;
   for (int32_t s = 0; s < batch; ++s) {
     const snap_sample_desc& d = p->descs[s];
-    if (d.nx < 1 || d.nt < 1 || d.ny != 1 || d.var_off < 0 || d.row_off < 0 || d.aux_off < 0) {
+    if (d.nx < 1 || d.nt < 1 || d.ny < 1 || d.var_off < 0 || d.row_off < 0 || d.aux_off < 0 ||
+        (d.ny != 1 && d.family != SNAP_DIFF2D_ENERGY)) {
       free_plan(p); return SNAP_EINVAL;
     }
     const int64_t m = rows_of(d);
@@ -381,6 +390,11 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
       if (cls > 0) need = band_workspace_bytes(d.nx, d.nt, mixed);
       // factorization work ~ rows x (block bandwidth)^2
       cost[s] = (double)d.nx * (d.nt - 1) * (double)(cls + 1) * (cls + 1) * 256.0;
+    } else if (d.family == SNAP_DIFF2D_ENERGY) {
+      kind = 2;
+      cls = (d.dt > 0.0 && d.dx > 0.0 && d.p0 >= 0.0 && spec_supported(d.nx, d.ny, d.nt)) ? 0 : -1;
+      if (cls == 0) need = spec_workspace_bytes(d.nx, d.nt);
+      cost[s] = (double)d.nx * d.ny * 16.0 * 40.0;
     }
     if (cls < 0) { free_plan(p); return SNAP_EUNSUPPORTED; }
     p->ws_off[s] = (int64_t)ws;
@@ -420,6 +434,42 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
     p->streams.resize(ns, nullptr);
     for (auto& st : p->streams)
       if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) { free_plan(p); return SNAP_EHIP; }
+  }
+
+  bool spectral = false;
+  for (const auto& g : p->groups) spectral |= g.kind == 2;
+  if (spectral) {
+    // orthonormal real Fourier bases Q[x][j] and s_j = sin^2(pi f_j / N) for
+    // N = 16, 32, 48, 64, packed as the kernel expects
+    std::vector<double> tab;
+    for (int n : {16, 32, 48, 64}) {
+      const int half = n / 2;
+      const double pi = 3.14159265358979323846;
+      std::vector<double> q((size_t)n * n), s2(n);
+      for (int x = 0; x < n; ++x)
+        for (int j = 0; j < n; ++j) {
+          double v;
+          if (j == 0) v = 1.0 / std::sqrt((double)n);
+          else if (j == half) v = (x % 2 ? -1.0 : 1.0) / std::sqrt((double)n);
+          else {
+            const int k = j < half ? j : j - half;
+            const double ang = 2.0 * pi * (double)((k * x) % n) / n;
+            v = std::sqrt(2.0 / n) * (j < half ? std::cos(ang) : std::sin(ang));
+          }
+          q[(size_t)x * n + j] = v;
+        }
+      for (int j = 0; j < n; ++j) {
+        const int f = j <= half ? j : j - half;
+        const double sn = std::sin(pi * f / n);
+        s2[j] = sn * sn;
+      }
+      tab.insert(tab.end(), q.begin(), q.end());
+      tab.insert(tab.end(), s2.begin(), s2.end());
+    }
+    if (hipMalloc(&p->d_tab, sizeof(double) * tab.size()) != hipSuccess ||
+        hipMemcpy(p->d_tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      free_plan(p); return SNAP_ENOMEM;
+    }
   }
 
   if (batch > 0) {
@@ -480,6 +530,8 @@ int launch_group_cls(const snap_plan_s& p, KernelArgs a, const Group& g, int cls
   const bool mixed = p.opt.precision == SNAP_PREC_MIXED;
   a.order = g.d_ids;
   a.count = (int32_t)g.ids.size();
+  a.tab = p.d_tab;
+  if (g.kind == 2) return spec_launch(a, st);
   return g.kind == 0 ? slab_launch(a, cls, mixed, st) : band_launch(a, cls, mixed, st);
 }
 }  // namespace
@@ -520,8 +572,9 @@ static bool same_call(const KernelArgs& x, const KernelArgs& y) {
 // captured through its events).
 static int run_graph(snap_plan plan, const KernelArgs& a, hipStream_t st) {
   if (st == nullptr) return run(plan, a, st);   // the null stream cannot be captured
-  // one slab-row group is one kernel launch: a graph would only add its replay
-  if (plan->groups.size() == 1 && plan->groups[0].kind == 0) return run(plan, a, st);
+  // one slab-row or spectral group is one kernel launch: a graph would only
+  // add its replay
+  if (plan->groups.size() == 1 && plan->groups[0].kind != 1) return run(plan, a, st);
   std::lock_guard<std::mutex> lock(plan->graph_mu);
   GraphSlot& g = plan->graphs[a.backward ? 1 : 0];
   if (!g.exec || !same_call(g.key, a)) {
@@ -627,8 +680,8 @@ int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed) {
     const Group& g = plan->groups[i];
     char line[160];
     std::snprintf(line, sizeof(line), "group %zu: %s class %d, %d wavefronts per workgroup, %zu samples\n",
-                  i, g.kind == 0 ? "slab" : "band", g.cls,
-                  g.kind == 0 ? slab_waves(g.cls) : band_waves(g.cls), g.ids.size());
+                  i, g.kind == 0 ? "slab" : (g.kind == 1 ? "band" : "spectral"), g.cls,
+                  g.kind == 0 ? slab_waves(g.cls) : (g.kind == 1 ? band_waves(g.cls) : 16), g.ids.size());
     t += line;
   }
   if (needed) *needed = t.size();
@@ -746,6 +799,7 @@ const char* snap_status_string(int status) {
     case SNAP_ST_LS_FAIL: return "line_search_failed";
     case SNAP_ST_NONFINITE: return "nonfinite";
     case SNAP_ST_SINGULAR_PIVOT: return "singular_pivot";
+    case SNAP_ST_HESSIAN_FLOOR: return "hessian_floor";
     default: return "unknown";
   }
 }

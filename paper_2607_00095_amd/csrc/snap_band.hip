@@ -983,7 +983,9 @@ SNAP_BAND_KERNEL void band_step(KernelArgs A) {
     const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (ht - h1);
     // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
     // ||h||_1 along p sits below the rounding of the row sums
-    if (dphi_t <= 1e-4 * alpha * dphi || !(dphi < 0.0) || hinf <= 1e-6) { ok = 1; break; }
+    // (with W >= 0.1 the step is a descent direction of the merit unless it
+    // is zero; a zero step is taken, any other step must pass the test)
+    if (dphi_t <= 1e-4 * alpha * dphi || !(pp > 0.0) || hinf <= 1e-6) { ok = 1; break; }
     alpha *= 0.5;
     ++backtracks;
   }
@@ -1064,13 +1066,19 @@ SNAP_BAND_KERNEL void band_adjoint(KernelArgs A) {
     bad = factor_sweep<BB, NW, R>(C, WL, sh);
   }
   const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, !have, lamp);
+  int floored = 0;
   for (int v = threadIdx.x; v < C.n; v += NT) {
     const int k = v / C.nx, x = v - k * C.nx;
     A.grad_uhat[D.var_off + v] = (C.g[v] - jt_at(C, lamp, k, x)) / w_at(C, k, x);
+    if (k <= C.nt - 2) {
+      const double* L = C.lam + (size_t)k * C.nx;
+      floored |= 1.0 + C.q * (L[wrap(x - 1, C.nx)] - L[wrap(x + 1, C.nx)]) < kWFloor;
+    }
   }
+  floored = __syncthreads_or(floored);
   if (threadIdx.x == 0) {
     snap_sample_stats st;
-    st.status = bad ? SNAP_ST_SINGULAR_PIVOT : SNAP_ST_CONVERGED;
+    st.status = bad ? SNAP_ST_SINGULAR_PIVOT : (floored ? SNAP_ST_HESSIAN_FLOOR : SNAP_ST_CONVERGED);
     st.newton_iters = 0; st.ls_backtracks = 0; st.refine_steps = refines;
     st.h_inf = 0.0; st.stat_inf = 0.0;
     A.stats[sid] = st;

@@ -26,6 +26,7 @@ struct KernelArgs {
   const int64_t* ws_off;           // per-sample byte offset of its workspace block (or null)
   snap_options opt;
   int32_t backward;                // 0 = forward projection, 1 = adjoint
+  const double* tab;               // Fourier basis tables of the 2D family (or null)
 };
 
 __device__ __forceinline__ double bcast_first(double v) {

@@ -383,14 +383,17 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
   }
   // the adjoint takes W at lam*, and its right-hand side J W^{-1} grad_u only,
   // so the multipliers entering the stationarity residual are zero
+  int floored = 0;   // adjoint: exact W below the floor somewhere
   for (int k = tid; k < kMaxNt; k += NT) {
     const double l = (bwd && k < nr) ? A.lam[D.row_off + nx + k] : 0.0;
     const double wk = wslab(k, l);
+    floored |= k < nr && 1.0 + 2.0 * c * l < kWFloor;
     sh.W[k] = wk;
     sh.rW[k] = rcp_nr(wk);
     sh.lam[k] = 0.0;
     sh.lamp[k] = 0.0;
   }
+  floored = __syncthreads_or(floored);
   // Slab sums at a point, in one of two forms (the pass kind is a
   // compile-time constant, so each call site gets its own code):
   //   kPoint  the point u with multipliers lamv (slab rows), lamicv (IC rows);
@@ -598,7 +601,9 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
         // (||h||_inf <= 1e-6): full Newton steps.
         const double dphi = dd - mu * h1cur;
         const double dphit = dd + 0.5 * pp + mu * (h1 - h1cur);
-        acc = (dphit <= 1e-4 * dphi) || !(dphi < 0.0) || hinf <= 1e-6;
+        // (with W >= 0.1 the step is a descent direction of the merit unless
+        // it is zero; a zero step is taken, any other must pass the test)
+        acc = (dphit <= 1e-4 * dphi) || !(pp > 0.0) || hinf <= 1e-6;
         // rejected: a second-order correction is tried only when the full step
         // increased the constraint violation (the curvature of h is what failed)
         soc = SOC && !acc && h1 > h1cur;
@@ -913,7 +918,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           for (int q = 0; q < NW; ++q) { pp += sh.red[q][1]; dd += sh.red[q][2]; }
           const double dphi = dd - mu * h1cur;
           const double dphit = alpha * dd + 0.5 * alpha * alpha * pp + mu * (h1_rows() - h1cur);
-          const int good = (dphit <= 1e-4 * alpha * dphi) || !(dphi < 0.0) ? 1 : 0;
+          const int good = (dphit <= 1e-4 * alpha * dphi) || !(pp > 0.0) ? 1 : 0;
           if (lane == 0) sh.flag[3] = good;
         }
         lds_barrier();
@@ -971,7 +976,7 @@ __global__ __launch_bounds__(NW * kWave, 1) void slab_kernel(KernelArgs A) {
           }
         }
       }
-      status = SNAP_ST_CONVERGED;
+      status = floored ? SNAP_ST_HESSIAN_FLOOR : SNAP_ST_CONVERGED;
       break;
     }
     // ------------------------------------------------ step and trial point at alpha = 1

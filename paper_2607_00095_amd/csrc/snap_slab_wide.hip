@@ -169,13 +169,16 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_wide_kernel(KernelArgs A
     lamic[j] = (bwd && w == 0 && x < nx) ? A.lam[D.row_off + x] : 0.0;
     lampic[j] = 0.0;
   }
+  int floored = 0;   // adjoint: exact W below the floor somewhere
   for (int k = threadIdx.x; k < kMaxNt; k += kSlabThreads) {
     double l = (bwd && k < nr) ? A.lam[D.row_off + nx + k] : 0.0;
     sh.lam[k] = l;
     sh.lamp[k] = 0.0;
     double wk = (k < nr) ? 1.0 + 2.0 * c * l : 1.0;
+    floored |= k < nr && wk < wfloor;
     sh.W[k] = fmax(wk, wfloor);
   }
+  floored = __syncthreads_or(floored);
   if (bwd) {
     // W is taken at lam*; the adjoint right-hand side uses J W^{-1} grad_u only,
     // so the multipliers entering the stationarity residual are zero
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_wide_kernel(KernelArgs A
           if (x < nx) A.grad_uhat[D.var_off + (int64_t)k * nx + x] = step_at(s, j, k, u[s][j]);
         }
       }
-      status = SNAP_ST_CONVERGED;
+      status = floored ? SNAP_ST_HESSIAN_FLOOR : SNAP_ST_CONVERGED;
       break;
     }
 
@@ -463,7 +466,9 @@ __global__ __launch_bounds__(kSlabThreads, 1) void slab_wide_kernel(KernelArgs A
         const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (h1 - h1_0);
         // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
         // ||h||_1 along p sits below the rounding of the row sums
-        int ok = (dphi_t <= 1e-4 * alpha * dphi) || !(dphi < 0.0) || hinf <= 1e-6 ? 1 : 0;
+        // (with W >= 0.1 the step is a descent direction of the merit unless
+        // it is zero; a zero step is taken, any other must pass the test)
+        int ok = (dphi_t <= 1e-4 * alpha * dphi) || !(pp > 0.0) || hinf <= 1e-6 ? 1 : 0;
         if (lane == 0) sh.flag[1] = ok;
       }
       lds_barrier();
