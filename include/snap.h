@@ -262,6 +262,27 @@ int snap_plan_group_classes(snap_plan plan, int32_t group, int32_t* classes, int
  * plan).  Drops any captured graph.  Must not race with calls on the plan. */
 int snap_plan_set_group_class(snap_plan plan, int32_t group, int32_t cls);
 
+/* Steps of the constrained flow-matching sampler around the projection
+ * (paper Sec. II-A, sampling loop over N substeps of flow time: shoot to
+ * flow time 1 with the velocity, project, pull back along the straight-line
+ * interpolant).  Elementwise over n packed float64 values (device pointers,
+ * caller-owned, stream-ordered); outputs must not alias inputs except where
+ * stated.  Return SNAP_EINVAL for a bad size, pointer or time.
+ *
+ * snap_flow_velocity_gaussian: v = m + c(tau) (u - tau m),
+ *   c(tau) = (tau s^2 - (1 - tau)) / ((1 - tau)^2 + tau^2 s^2), the exact
+ *   marginal velocity E[x1 - x0 | x_tau = u] of the straight-line interpolant
+ *   between x0 ~ N(0, I) and x1 ~ N(m, s^2 I): a closed-form stand-in for a
+ *   trained velocity network (0 <= tau <= 1, s > 0).
+ * snap_flow_shoot: u1_hat = u_tau + (1 - tau) v (u1_hat may alias u_tau).
+ * snap_flow_pullback: u_tau' = u0 + tau' (u1 - u0) (u_tau' may alias u1). */
+int snap_flow_velocity_gaussian(int64_t n, const double* u, const double* mean, double tau, double s,
+                                double* v, void* stream);
+int snap_flow_shoot(int64_t n, const double* u_tau, const double* v, double tau, double* u1_hat,
+                    void* stream);
+int snap_flow_pullback(int64_t n, const double* u0, const double* u1, double tau_next, double* u_tau,
+                       void* stream);
+
 /* Kernel timing (a tracing aid; not needed for projection).  With timing
  * enabled, snap_project and snap_project_backward record a HIP event on the
  * launch stream before and after every launch of the timed kernels

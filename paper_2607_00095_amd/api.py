@@ -74,6 +74,10 @@ def _load():
     lib.snap_plan_set_kernel_timing.argtypes = [vp, i32]
     lib.snap_plan_kernel_times.argtypes = [vp, i32, dp, C.POINTER(i64), C.POINTER(i64)]
     lib.snap_plan_reset_kernel_times.argtypes = [vp]
+    lib.snap_flow_velocity_gaussian.argtypes = [i64, vp, vp, C.c_double, C.c_double, vp, vp]
+    lib.snap_flow_shoot.argtypes = [i64, vp, vp, C.c_double, vp, vp]
+    lib.snap_flow_pullback.argtypes = [i64, vp, vp, C.c_double, vp, vp]
+    lib.snap_project_noalloc.argtypes = [vp] * 7
     lib.snap_error_string.argtypes = [C.c_int]
     lib.snap_error_string.restype = C.c_char_p
     lib.snap_status_string.argtypes = [C.c_int]
@@ -81,7 +85,8 @@ def _load():
     for f in ("snap_plan_create", "snap_plan_workspace_bytes", "snap_plan_sizes", "snap_project",
               "snap_project_backward", "snap_plan_destroy", "snap_plan_describe",
               "snap_plan_group_classes", "snap_plan_set_group_class", "snap_plan_set_kernel_timing",
-              "snap_plan_kernel_times", "snap_plan_reset_kernel_times"):
+              "snap_plan_kernel_times", "snap_plan_reset_kernel_times", "snap_flow_velocity_gaussian",
+              "snap_flow_shoot", "snap_flow_pullback", "snap_project_noalloc"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -236,6 +241,44 @@ def project_backward(plan: Plan, u: torch.Tensor, lam: torch.Tensor, aux: Option
                                      _ptr(grad_u), _ptr(g), _ptr(st), C.c_void_p(s.cuda_stream)),
            "snap_project_backward")
     return g, st
+
+
+def pcfm_sample(plan: Plan, u0: torch.Tensor, mean: torch.Tensor, s: float, nsteps: int,
+                aux: Optional[torch.Tensor], stream: Optional[torch.cuda.Stream] = None):
+    """Constrained flow-matching sampler (paper Sec. II-A) over `nsteps`
+    uniform substeps of flow time, with the closed-form Gaussian velocity:
+    shoot to flow time 1, project every sample with `plan`, pull back along
+    the straight-line interpolant.  The plan and one workspace serve every
+    substep.  Returns (sample, stats of the last projection, number of
+    samples that converged in every substep)."""
+    lib = _load()
+    n = plan.total_vars
+    _dev_f64(u0, n, "u0", plan.device)
+    _dev_f64(mean, n, "mean", plan.device)
+    if nsteps < 1:
+        raise SnapError("nsteps must be >= 1")
+    dev = plan.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    sp = C.c_void_p(st.cuda_stream)
+    u = u0.clone()
+    v = torch.empty_like(u)
+    u1 = torch.empty_like(u)
+    lam = torch.empty(max(plan.total_rows, 1), dtype=torch.float64, device=dev)
+    stats = torch.empty(max(plan.batch, 1) * STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    ok_all = torch.ones(max(plan.batch, 1), dtype=torch.bool, device=dev)
+    ws = plan.new_workspace()
+    for j in range(nsteps):
+        tau, tau_next = j / nsteps, (j + 1) / nsteps
+        _check(lib.snap_flow_velocity_gaussian(n, _ptr(u), _ptr(mean), tau, s, _ptr(v), sp),
+               "snap_flow_velocity_gaussian")
+        _check(lib.snap_flow_shoot(n, _ptr(u), _ptr(v), tau, _ptr(v), sp), "snap_flow_shoot")
+        project(plan, v, aux, ws, u1, lam, stats, st)
+        status = stats.view(torch.int32).view(-1, STATS_DTYPE.itemsize // 4)[: plan.batch, 0]
+        ok_all &= status[: plan.batch] == 0
+        if j + 1 < nsteps:
+            _check(lib.snap_flow_pullback(n, _ptr(u0), _ptr(u1), tau_next, _ptr(u), sp),
+                   "snap_flow_pullback")
+    return u1, stats, ok_all
 
 
 def stats_to_numpy(stats: torch.Tensor, batch: int) -> np.ndarray:

@@ -285,6 +285,11 @@ def upstream_grad(b: Batch, seed: int = 7) -> np.ndarray:
     return _rng(seed).standard_normal(b.total_vars)
 
 
+def prior_sample(b: Batch, seed: int = 11) -> np.ndarray:
+    """N(0,1) draw from the flow's source distribution, packed like the variables."""
+    return _rng(seed).standard_normal(b.total_vars)
+
+
 # the five benchmark configurations, by name, at full size
 CONFIGS = {
     "mass_ic": dict(fn=mass_ic_batch, kw=dict(batch=32, nx=64, nt=32, seed=1001)),
