@@ -318,6 +318,23 @@ __device__ __forceinline__ void scatter_row(int I, int a, const int* col, const 
   }
 }
 
+// The value itself, as a fresh scalar at this point of the program: offsets
+// derived from it are recomputed here (one scalar add) instead of being hoisted
+// out of the step loop, where four LDS addresses per accumulator slot would
+// take the registers the accumulator window needs.
+// (x must be uniform over the wavefront.)
+__device__ __forceinline__ int fresh(int x) {
+  x = __builtin_amdgcn_readfirstlane(x);
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
+// the same for a per-lane value
+__device__ __forceinline__ int fresh_v(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // ------------------------------------------------------------------ factor
 // Factor S at the current (u, lam) with the fused forward substitution of the
 // right-hand side; writes L blocks, D, y = L^{-1} r, rvec (canonical rhs) and
@@ -441,8 +458,9 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     for (int s = 0; s < SPW; ++s) {
       if (sd[s] < 0) continue;
       if (tr[s] == 0) {
+        const int d = fresh(sd[s]);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sh.P[sd[s]][Mfma<R>::row(lk, e) * kLd + li] = acc[s][e];
+        for (int e = 0; e < 4; ++e) sh.P[d][Mfma<R>::row(lk, e) * kLd + li] = acc[s][e];
       }
     }
     zero_nr();
@@ -459,7 +477,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       // the identity lanes turn into the columns of X = L^{-1}.  Row p of X is
       // final after pivot p: T = L^{-T} D^{-1} and the stored X are written as
       // the sweep goes.  (Lanes 32..63 repeat lanes 0..31.)
-      const int k = lane & (kT - 1);
+      const int k = fresh_v(lane & (kT - 1));  // (not hoisted: 16 identity values would be)
       const bool xl = (lane & 16) != 0;        // an identity / X lane
       double dmine = 1.0;
       int nonpos = 0;
@@ -500,9 +518,9 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     // (c) panel solve L(J+d, J) = S(J+d, J) T for d >= 1
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
-      const int d = sd[s];
-      if (d < 1) continue;
+      if (sd[s] < 1) continue;
       if (tr[s] != 0) continue;
+      const int d = fresh(sd[s]);
       V res = V{0, 0, 0, 0};
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
@@ -532,12 +550,11 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     }
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
-      const int d = sd[s];
-      if (d < 0) continue;
+      if (sd[s] < 0) continue;
       if (tr[s] == 0) {
-        load_nr(s, d);                       // retire panel block, take the entering one
+        load_nr(s, fresh(sd[s]));            // retire panel block, take the entering one
       } else {
-        const int dk = tr[s], di = tr[s] + d;    // K - J and I - J: 1 <= dk <= di <= BB
+        const int dk = tr[s], di = tr[s] + fresh(sd[s]);  // K - J and I - J: 1 <= dk <= di <= BB
         V v = acc[s];
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
