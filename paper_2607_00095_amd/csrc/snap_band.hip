@@ -78,6 +78,7 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 template <int BB, int NW, typename R>
 struct BandShared {
   R P[BB + 1][kTL];        // panel blocks (S, then L after the panel solve)
+  R PD[BB + 1][kTL];       // -L(J+d, J) D_J, the trailing update's right operand
   R NR[BB + 1][kTL];       // staging area of the entering block row
   R T[kTL];                // L_JJ^{-T} D_J^{-1}
   double Xw[kTL];          // L_JJ^{-1} (solves)
@@ -529,9 +530,11 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
         res = Mfma<R>::mma(av, bv, res);
       }
       R* Lgd = Lg + ((size_t)J * (BB + 1) + d) * 256;
+      const R dl = -(R)sh.Dv[li];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         sh.P[d][Mfma<R>::row(lk, e) * kLd + li] = res[e];
+        sh.PD[d][Mfma<R>::row(lk, e) * kLd + li] = dl * res[e];
         Lgd[Mfma<R>::row(lk, e) * kT + li] = res[e];
       }
     }
@@ -558,8 +561,8 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
         V v = acc[s];
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-          const R av = -sh.P[di][li * kLd + 4 * qq + lk];
-          const R bv = (R)sh.Dv[4 * qq + lk] * sh.P[dk][li * kLd + 4 * qq + lk];
+          const R av = sh.P[di][li * kLd + 4 * qq + lk];
+          const R bv = sh.PD[dk][li * kLd + 4 * qq + lk];
           v = Mfma<R>::mma(av, bv, v);
         }
         acc[s] = v;
