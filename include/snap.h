@@ -246,14 +246,20 @@ int snap_project_backward(snap_plan plan, const double* u, const double* lambda,
                           double* grad_uhat, snap_sample_stats* stats, void* stream);
 
 /* Text description of the plan's launch groups, one line per group
- * ("group <i>: <slab|band> class <c>, <w> wavefronts per workgroup, <n> samples").
+ * ("group <i>: <slab|band|spectral> class <c>, <w> wavefronts per workgroup
+ * [, two-sided factorization], <n> samples").
  * Writes at most len bytes into buf (NUL-terminated when len > 0); *needed, if
  * not NULL, receives the full length without the NUL. */
 int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed);
 
 /* Kernel classes (launch shapes) that can run launch group `group` of the plan,
  * the one in use first; *count receives how many there are (at most cap are
- * written).  Groups are numbered as in snap_plan_describe. */
+ * written).  Groups are numbered as in snap_plan_describe.  Banded family:
+ * class BB (block half-bandwidth, default shape), BB + 32 (the other
+ * wavefront count, BB <= 9), BB + 64 (two-sided factorization, float64,
+ * BB >= 13: two workgroups per sample factor the band from both ends toward
+ * a separator, which halves the chain of dependent panel steps; the default
+ * for bands of at least 40 BB block rows). */
 int snap_plan_group_classes(snap_plan plan, int32_t group, int32_t* classes, int32_t cap,
                             int32_t* count);
 

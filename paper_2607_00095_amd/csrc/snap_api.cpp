@@ -21,13 +21,14 @@
 namespace snap {
 int slab_class(int nx, int nt);
 int slab_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st);
-int band_class(int nx, int nt);
+int band_class(int nx, int nt, bool mixed);
 int band_launch(const KernelArgs& a, int cls, bool mixed, hipStream_t st);
 size_t band_workspace_bytes(int nx, int nt, bool mixed);
 int slab_variants(int nx, int nt, int* out, int cap);
-int band_variants(int cls, int* out, int cap);
+int band_variants(int nx, int nt, bool mixed, int* out, int cap);
 int slab_waves(int cls);
 int band_waves(int cls);
+int band_sides(int cls);
 bool spec_supported(int nx, int ny, int nt);
 size_t spec_workspace_bytes(int nx, int nt);
 int spec_launch(const KernelArgs& a, hipStream_t st);
@@ -80,7 +81,7 @@ struct Group {
 };
 
 constexpr int kStreams = 4;   // groups are spread over this many internal streams
-constexpr int kTimerEvents = 8192;   // event pool of the kernel timer
+constexpr int kTimerEvents = 32768;  // event pool of the kernel timer
 
 // A captured launch sequence and the call arguments it was captured with.
 struct GraphSlot {
@@ -189,7 +190,8 @@ std::vector<int> group_candidates(const snap_plan_s& p, const Group& g) {
     const snap_sample_desc& d = p.descs[g.ids[i]];
     int v[8];
     const int n = g.kind == 0 ? slab_variants(d.nx, d.nt, v, 8)
-                  : g.kind == 1 ? band_variants(g.cls, v, 8) : (v[0] = 0, 1);
+                  : g.kind == 1 ? band_variants(d.nx, d.nt, p.opt.precision == SNAP_PREC_MIXED, v, 8)
+                                : (v[0] = 0, 1);
     std::vector<int> mine(v, v + n);
     if (i == 0) {
       cand = mine;
@@ -386,10 +388,10 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
       cost[s] = (double)d.nx * d.nt;
     } else if (d.family == SNAP_BURGERS_LF) {
       kind = 1;
-      cls = (d.dt > 0.0 && d.dx > 0.0) ? band_class(d.nx, d.nt) : -1;
+      cls = (d.dt > 0.0 && d.dx > 0.0) ? band_class(d.nx, d.nt, mixed) : -1;
       if (cls > 0) need = band_workspace_bytes(d.nx, d.nt, mixed);
       // factorization work ~ rows x (block bandwidth)^2
-      cost[s] = (double)d.nx * (d.nt - 1) * (double)(cls + 1) * (cls + 1) * 256.0;
+      cost[s] = (double)d.nx * (d.nt - 1) * (double)(cls % 32 + 1) * (cls % 32 + 1) * 256.0;
     } else if (d.family == SNAP_DIFF2D_ENERGY) {
       kind = 2;
       cls = (d.dt > 0.0 && d.dx > 0.0 && d.p0 >= 0.0 && spec_supported(d.nx, d.ny, d.nt)) ? 0 : -1;
@@ -678,10 +680,11 @@ int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed) {
   std::string t;
   for (size_t i = 0; i < plan->groups.size(); ++i) {
     const Group& g = plan->groups[i];
-    char line[160];
-    std::snprintf(line, sizeof(line), "group %zu: %s class %d, %d wavefronts per workgroup, %zu samples\n",
+    char line[192];
+    std::snprintf(line, sizeof(line), "group %zu: %s class %d, %d wavefronts per workgroup%s, %zu samples\n",
                   i, g.kind == 0 ? "slab" : (g.kind == 1 ? "band" : "spectral"), g.cls,
-                  g.kind == 0 ? slab_waves(g.cls) : (g.kind == 1 ? band_waves(g.cls) : 16), g.ids.size());
+                  g.kind == 0 ? slab_waves(g.cls) : (g.kind == 1 ? band_waves(g.cls) : 8),
+                  g.kind == 1 && band_sides(g.cls) == 2 ? ", two-sided factorization" : "", g.ids.size());
     t += line;
   }
   if (needed) *needed = t.size();

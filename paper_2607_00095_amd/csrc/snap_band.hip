@@ -30,6 +30,8 @@
 //
 // Precision R: double (plain form) or float (mixed form: float32 factor and
 // solves, float64 residual r - S x from the stencil, iterative refinement).
+#include <type_traits>
+
 #include "snap_device.hpp"
 
 namespace snap {
@@ -106,7 +108,9 @@ struct Ctx {
 
 // workspace layout of one sample (byte offsets, 256-aligned)
 struct WsLayout {
-  size_t hdr, L, Dg, Y, rin, rvec, lamp, p, t, res, acol, aval, total;
+  size_t hdr, L, Dg, Y, rin, rvec, lamp, p, t, res, acol, aval;
+  size_t scol, sval, sepw, sepr;   // two-sided form: separator rows, exported updates
+  size_t total;
 };
 
 constexpr int kContrib = 16;   // stencil contributions to one row of S (4 variables x 4 rows)
@@ -136,6 +140,14 @@ __host__ __device__ inline WsLayout ws_layout(int nx, int nt, int BB, size_t rsi
   w.res = o; o += align256(m * 8);
   w.acol = o; o += align256(M * kContrib * 4);
   w.aval = o; o += align256(M * kContrib * 8);
+  // two-sided form: the bottom sweep's copy of the separator rows' stencil
+  // contributions, and each side's update of the separator (its lower block
+  // triangle, BB(BB+1)/2 blocks, and its right-hand side)
+  const size_t sr = (size_t)BB * kT, nsb = (size_t)BB * (BB + 1) / 2;
+  w.scol = o; o += align256(sr * kContrib * 4);
+  w.sval = o; o += align256(sr * kContrib * 8);
+  w.sepw = o; o += align256(2 * nsb * 256 * 8);
+  w.sepr = o; o += align256(2 * sr * 8);
   w.total = o;
   return w;
 }
@@ -234,20 +246,21 @@ __device__ __forceinline__ double block_max(double v, double (*red)[4], int slot
 // column of r' (a column may appear more than once when Nx is tiny; the
 // scatter adds them).  Computed for all rows in one parallel pass before the
 // factorization, so the factorization only scatters prefetched pairs.
+// Rows [r0, r1) go to entries r - base of (cols, vals); with `rhs` their
+// right-hand sides are written too (rin and rvec).
 template <int NW>
-__device__ void assemble_all(const Ctx& C, const WsLayout& WL) {
-  int* acol = (int*)(C.ws + WL.acol);
-  double* aval = (double*)(C.ws + WL.aval);
+__device__ void assemble_rows(const Ctx& C, const WsLayout& WL, int r0, int r1, int* cols, double* vals,
+                              int base, bool rhs_out) {
   double* rvec = (double*)(C.ws + WL.rvec);
   double* rin = (double*)(C.ws + WL.rin);
   const int nx = C.nx;
-  for (int r = threadIdx.x; r < C.M; r += NW * kWave) {
-    int* col = acol + (size_t)r * kContrib;
-    double* val = aval + (size_t)r * kContrib;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += NW * kWave) {
+    int* col = cols + (size_t)(r - base) * kContrib;
+    double* val = vals + (size_t)(r - base) * kContrib;
     if (r >= C.m) {                    // padding row: identity
 #pragma unroll
       for (int t = 0; t < kContrib; ++t) { col[t] = r; val[t] = t == 0 ? 1.0 : 0.0; }
-      rin[r] = 0.0;
+      if (rhs_out) rin[r] = 0.0;
       continue;
     }
     const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
@@ -273,10 +286,17 @@ __device__ void assemble_all(const Ctx& C, const WsLayout& WL) {
       col[4 * e + 3] = own ? kk * nx + pos_of(wrap(y + 1, nx), nx) : r;
       val[4 * e + 3] = own ? sv * (-C.q * uy - C.c) : 0.0;
     }
-    rvec[(size_t)k * nx + x] = rhs;
-    rin[r] = rhs;
+    if (rhs_out) {
+      rvec[(size_t)k * nx + x] = rhs;
+      rin[r] = rhs;
+    }
   }
   __syncthreads();
+}
+
+template <int NW>
+__device__ void assemble_all(const Ctx& C, const WsLayout& WL) {
+  assemble_rows<NW>(C, WL, 0, C.M, (int*)(C.ws + WL.acol), (double*)(C.ws + WL.aval), 0, true);
 }
 
 // Right-hand side h - J W^{-1} g alone (rvec canonical, rin internal order),
@@ -336,12 +356,108 @@ __device__ __forceinline__ int fresh_v(int x) {
   return x;
 }
 
+// ------------------------------------------------------------------ parts
+// The two-sided form splits the block rows into a top part [0, K), a
+// separator [K, K+BB) and a bottom part [K+BB, NB).  One workgroup factors the
+// top downwards, another the bottom upwards (as the row-and-column reversed
+// matrix, which has the same band).  The parts do not touch (their rows are
+// more than BB blocks apart); each leaves its Schur complement update of the
+// separator in the workspace, and a third sweep factors the separator (its
+// own entries plus both updates) last.  That is the LDL^T factorization of S
+// with the rows ordered top, bottom reversed, separator: the flops of the
+// one-sided sweep, half its chain of dependent panel steps.
+enum PartKind { kWhole = 0, kTop = 1, kBottom = 2, kSep = 3 };
+
+struct Part {
+  int kind;
+  int K, Kb;     // first separator block row; block rows of the bottom part
+  int steps;     // panel steps of the sweep
+  int rows;      // block rows (sweep coordinates) that enter; later ones are zero
+};
+
+template <int BB>
+__device__ __forceinline__ Part make_part(const Ctx& C, int kind) {
+  Part P;
+  P.kind = kind;
+  P.K = (C.NB - BB) / 2;
+  P.Kb = C.NB - P.K - BB;
+  P.steps = kind == kWhole ? C.NB : (kind == kTop ? P.K : (kind == kBottom ? P.Kb : BB));
+  P.rows = kind == kWhole ? C.NB : (kind == kTop ? P.K + BB : (kind == kBottom ? P.Kb + BB : BB));
+  return P;
+}
+
+// block index under which panel J of a sweep stores L, D and y
+__device__ __forceinline__ int part_slot(const Ctx& C, const Part& P, int J) {
+  return P.kind == kBottom ? C.NB - 1 - J : (P.kind == kSep ? P.K + J : J);
+}
+
+constexpr int kNoCol = 0x3fffffff;   // a contribution the sweep leaves out
+
+// Contributions t0 .. t0+NC-1 of row a of block row I, both in sweep
+// coordinates.  The bottom sweep takes only a separator row's coupling to
+// the bottom part; the rest of the separator rows is the top's.
+template <int NC>
+__device__ __forceinline__ void part_row(const Ctx& C, const WsLayout& WL, const Part& P, int I, int a, int t0,
+                                         int* cl, double* vl) {
+  if (I >= P.rows) {
+#pragma unroll
+    for (int t = 0; t < NC; ++t) { cl[t] = kNoCol; vl[t] = 0.0; }
+    return;
+  }
+  if (P.kind != kBottom) {
+    const size_t o = ((size_t)I * kT + a) * kContrib + t0;
+    const int* col = (const int*)(C.ws + WL.acol) + o;
+    const double* val = (const double*)(C.ws + WL.aval) + o;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) { cl[t] = col[t]; vl[t] = val[t]; }
+    return;
+  }
+  const int r = C.M - 1 - (I * kT + a);          // the row in the matrix's own order
+  const bool sep = I >= P.Kb;
+  const size_t o = (size_t)(sep ? r - P.K * kT : r) * kContrib + t0;
+  const int* col = (const int*)(C.ws + (sep ? WL.scol : WL.acol)) + o;
+  const double* val = (const double*)(C.ws + (sep ? WL.sval : WL.aval)) + o;
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    const int c = C.M - 1 - col[t];
+    cl[t] = (sep && c >= P.Kb * kT) ? kNoCol : c;
+    vl[t] = val[t];
+  }
+}
+
+// right-hand side of row a of block row I (sweep coordinates)
+__device__ __forceinline__ double part_rhs(const Ctx& C, const double* rin, const Part& P, int I, int a) {
+  if (I >= P.rows) return 0.0;
+  if (P.kind == kBottom) return I < P.Kb ? rin[C.M - 1 - (I * kT + a)] : 0.0;
+  return rin[(size_t)I * kT + a];
+}
+
+// Entry [a][b] of separator block (i, i - d) (local block rows): the top's
+// export holds the separator's entries with the top's update, the bottom's
+// its own update in reversed coordinates, where the block is
+// (BB-1-(i-d), same d) and the entry [15-b][15-a].
+template <int BB>
+__device__ __forceinline__ double sep_entry(const double* sw, int i, int d, int a, int b) {
+  constexpr int NSB = BB * (BB + 1) / 2;
+  const int ib = BB - 1 - (i - d);
+  return sw[(size_t)(i * (i + 1) / 2 + d) * 256 + a * kT + b] +
+         sw[(size_t)(NSB + ib * (ib + 1) / 2 + d) * 256 + (15 - b) * kT + (15 - a)];
+}
+
+// separator right-hand side, local row i, entry a (both sides' exports)
+template <int BB>
+__device__ __forceinline__ double sep_rhs(const double* sr, int i, int a) {
+  return sr[i * kT + a] + sr[BB * kT + (BB - 1 - i) * kT + (15 - a)];
+}
+
 // ------------------------------------------------------------------ factor
-// Factor S at the current (u, lam) with the fused forward substitution of the
-// right-hand side; writes L blocks, D, y = L^{-1} r, rvec (canonical rhs) and
-// rin (internal-order rhs).  Returns 1 if a non-positive pivot was met.
+// Factor S (or the part PT of its two-sided form; the rows are assembled by
+// the caller) with the fused forward substitution of the right-hand side;
+// writes L blocks, D and y = L^{-1} r, and a top or bottom part exports its
+// update of the separator.  Returns 1 if a non-positive pivot was met.
 template <int BB, int NW, typename R>
-__device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh) {
+__device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh,
+                                                          const Part& PT) {
   using V = typename Mfma<R>::V;
   constexpr int NS = (BB + 1) * (BB + 2) / 2;
   constexpr int SPW = (NS + NW - 1) / NW;
@@ -402,27 +518,21 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     acc[s] = v;
   };
 
-  assemble_all<NW>(C, WL);
-  const int* acol = (const int*)(C.ws + WL.acol);
-  const double* aval = (const double*)(C.ws + WL.aval);
+  const double* sw_in = (const double*)(C.ws + WL.sepw);
+  const double* sr_in = (const double*)(C.ws + WL.sepr);
   // wavefront 1, lanes 0..15: row `lane` of the entering block row I, loaded
   // while wavefront 0 factors the diagonal block (which hides the latency)
   auto enter_row = [&](int I) {
-    const int r = I * kT + lane;
-    if (I < C.NB) {
+    if (I < PT.rows) {
       // two halves of eight contributions bound the registers this needs
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         int cl[kContrib / 2];
         double vl[kContrib / 2];
-#pragma unroll
-        for (int t = 0; t < kContrib / 2; ++t) {
-          cl[t] = acol[(size_t)r * kContrib + h * (kContrib / 2) + t];
-          vl[t] = aval[(size_t)r * kContrib + h * (kContrib / 2) + t];
-        }
+        part_row<kContrib / 2>(C, WL, PT, I, lane, h * (kContrib / 2), cl, vl);
         scatter_row<BB, R, kContrib / 2>(I, lane, cl, vl, sh.NR);
       }
-      sh.newr[lane] = rin[r];
+      sh.newr[lane] = part_rhs(C, rin, PT, I, lane);
     } else {
       sh.newr[lane] = 0.0;
     }
@@ -433,17 +543,23 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
   for (int I = 0; I <= BB; ++I) {
     zero_nr();
     lds_barrier();
-    if (threadIdx.x < kT) {
-      const int r = I * kT + threadIdx.x;
+    if (PT.kind == kSep) {
+      // the separator's block row I: both sides' exports (blocks left of the
+      // separator were eliminated by the sides)
+      if (I < BB) {
+        for (int e = threadIdx.x; e < (I + 1) * 256; e += NW * kWave) {
+          const int d = e >> 8, a = (e >> 4) & 15, b = e & 15;
+          sh.NR[d][a * kLd + b] = (R)sep_entry<BB>(sw_in, I, d, a, b);
+        }
+      }
+      if (threadIdx.x < kT)
+        sh.ring[(I % (BB + 1)) * kT + threadIdx.x] = I < BB ? sep_rhs<BB>(sr_in, I, threadIdx.x) : 0.0;
+    } else if (threadIdx.x < kT) {
       int cl[kContrib];
       double vl[kContrib];
-#pragma unroll
-      for (int t = 0; t < kContrib; ++t) {
-        cl[t] = (I < C.NB) ? acol[(size_t)r * kContrib + t] : -1;
-        vl[t] = (I < C.NB) ? aval[(size_t)r * kContrib + t] : 0.0;
-      }
+      part_row<kContrib>(C, WL, PT, I, threadIdx.x, 0, cl, vl);
       scatter_row<BB, R>(I, threadIdx.x, cl, vl, sh.NR);
-      sh.ring[(I % (BB + 1)) * kT + threadIdx.x] = (I < C.NB) ? rin[r] : 0.0;
+      sh.ring[(I % (BB + 1)) * kT + threadIdx.x] = part_rhs(C, rin, PT, I, threadIdx.x);
     }
     lds_barrier();
 #pragma unroll
@@ -453,7 +569,8 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
   }
 
   int bad = 0;
-  for (int J = 0; J < C.NB; ++J) {
+  for (int J = 0; J < PT.steps; ++J) {
+    const int sl = part_slot(C, PT, J);
     // (a) gather the panel column J into LDS; clear the staging area
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
@@ -486,7 +603,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
 #pragma unroll
       for (int i = 0; i < kT; ++i) v[i] = xl ? (i == k ? 1.0 : 0.0) : (double)sh.P[0][i * kLd + k];
       double rk = sh.ring[(J % (BB + 1)) * kT + k];
-      R* Lgd = Lg + ((size_t)J * (BB + 1)) * 256;
+      R* Lgd = Lg + ((size_t)sl * (BB + 1)) * 256;
 #pragma unroll
       for (int p = 0; p < kT; ++p) {
         const double dp = lane_bcast(v[p], p);   // A[p][p]
@@ -506,9 +623,9 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       if (lane < kT) {
         sh.Dv[k] = dmine;
         sh.rD[k] = rcp_nr(dmine);
-        Dg[(size_t)J * kT + k] = dmine;
+        Dg[(size_t)sl * kT + k] = dmine;
         sh.yJ[k] = rk;
-        Y[(size_t)J * kT + k] = rk;
+        Y[(size_t)sl * kT + k] = rk;
       }
       if (lane == 0 && nonpos) sh.flag[0] = 1;
     } else if (w == 1 && lane < kT) {
@@ -529,7 +646,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
         const R bv = sh.T[(4 * qq + lk) * kLd + li];
         res = Mfma<R>::mma(av, bv, res);
       }
-      R* Lgd = Lg + ((size_t)J * (BB + 1) + d) * 256;
+      R* Lgd = Lg + ((size_t)sl * (BB + 1) + d) * 256;
       const R dl = -(R)sh.Dv[li];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -544,7 +661,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     for (int t = threadIdx.x; t < kT * BB; t += NW * kWave) {
       const int d = 1 + t / kT, a = t - (d - 1) * kT;
       const int I = J + d;
-      if (I < C.NB) {
+      if (I < PT.rows) {
         double s = 0.0;
 #pragma unroll
         for (int cc = 0; cc < kT; ++cc) s += (double)sh.P[d][a * kLd + cc] * sh.yJ[cc];
@@ -574,6 +691,24 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
     advance();
     lds_barrier();
   }
+  if (PT.kind == kTop || PT.kind == kBottom) {
+    // export the window's separator blocks (local row d + tr, diagonal d) and
+    // the separator's right-hand side
+    constexpr int NSB = BB * (BB + 1) / 2;
+    double* sw = (double*)(C.ws + WL.sepw) + (PT.kind == kBottom ? (size_t)NSB * 256 : 0);
+    double* sr = (double*)(C.ws + WL.sepr) + (PT.kind == kBottom ? BB * kT : 0);
+#pragma unroll
+    for (int s = 0; s < SPW; ++s) {
+      if (sd[s] < 0) continue;
+      const int d = fresh(sd[s]), il = d + tr[s];
+      if (il >= BB) continue;
+      double* blk = sw + (size_t)(il * (il + 1) / 2 + d) * 256;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) blk[Mfma<R>::row(lk, e) * kT + li] = (double)acc[s][e];
+    }
+    for (int i = threadIdx.x; i < BB * kT; i += NW * kWave)
+      sr[i] = sh.ring[((PT.steps + i / kT) % (BB + 1)) * kT + (i % kT)];
+  }
   bad = sh.flag[0];
   __syncthreads();            // factor (global) visible to the sweeps
   if (threadIdx.x == 0) sh.flag[0] = 0;
@@ -582,32 +717,36 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
 }
 
 // ------------------------------------------------------------------ solves
-// forward substitution y = L^{-1} rin with the stored factor.  Threads
-// t < 16*BB own row (t % 16) of block L(J+1+t/16, J); threads 16*BB..16*BB+15
-// own a row of L_JJ^{-1}; each keeps its 16 values of the next panel in flight.
+// forward substitution y = L^{-1} rin with the stored factor (of the whole
+// matrix, or of the part PT of its two-sided form: a top or bottom part
+// exports its update of the separator's right-hand side, the separator's
+// sweep starts from both).  Threads t < 16*BB own row (t % 16) of block
+// L(J+1+t/16, J); threads 16*BB..16*BB+15 own a row of L_JJ^{-1}; each keeps
+// its 16 values of the next panel in flight.
 template <int BB, int NW, typename R>
 __device__ __attribute__((always_inline)) void forward_sweep(
-    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* rin, double* Y) {
+    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* rin, double* Y, const Part& PT) {
   static_assert(NW * kWave >= kT * (BB + 1), "forward sweep needs 16*(BB+1) threads");
   const R* Lg = (const R*)(C.ws + WL.L);
   const int t = threadIdx.x;
   const bool offd = t < kT * BB, diag = t >= kT * BB && t < kT * (BB + 1);
   const int d = offd ? 1 + t / kT : 0, a = offd ? t % kT : t - kT * BB;
+  const double* sr_in = (const double*)(C.ws + WL.sepr);
   for (int i = t; i < (BB + 1) * kT; i += NW * kWave) {
     const int I = i / kT, aa = i - I * kT;
-    sh.ring[i] = (I < C.NB) ? rin[(size_t)I * kT + aa] : 0.0;
+    sh.ring[i] = PT.kind == kSep ? (I < BB ? sep_rhs<BB>(sr_in, I, aa) : 0.0) : part_rhs(C, rin, PT, I, aa);
   }
   R cur[kT], nxt[kT];
   auto load = [&](int J, R* dst) {
-    if ((offd || diag) && J < C.NB) {
-      const R* src = Lg + ((size_t)J * (BB + 1) + d) * 256 + a * kT;
+    if ((offd || diag) && J < PT.steps) {
+      const R* src = Lg + ((size_t)part_slot(C, PT, J) * (BB + 1) + d) * 256 + a * kT;
 #pragma unroll
       for (int c = 0; c < kT; ++c) dst[c] = src[c];
     }
   };
   load(0, cur);
   lds_barrier();
-  for (int J = 0; J < C.NB; ++J) {
+  for (int J = 0; J < PT.steps; ++J) {
     load(J + 1, nxt);
     if (diag) {
       const double* rJ = &sh.ring[(J % (BB + 1)) * kT];
@@ -615,23 +754,24 @@ __device__ __attribute__((always_inline)) void forward_sweep(
 #pragma unroll
       for (int c = 0; c < kT; ++c) y += (double)cur[c] * rJ[c];
       sh.yJ[a] = y;
-      Y[(size_t)J * kT + a] = y;
+      Y[(size_t)part_slot(C, PT, J) * kT + a] = y;
     }
     lds_barrier();
-    if (offd && J + d < C.NB) {
+    if (offd && J + d < PT.rows) {
       double s = 0.0;
 #pragma unroll
       for (int c = 0; c < kT; ++c) s += (double)cur[c] * sh.yJ[c];
       sh.ring[((J + d) % (BB + 1)) * kT + a] -= s;
     }
     lds_barrier();
-    if (t < kT) {
-      const int I = J + BB + 1;
-      sh.ring[(J % (BB + 1)) * kT + t] = (I < C.NB) ? rin[(size_t)I * kT + t] : 0.0;
-    }
+    if (t < kT) sh.ring[(J % (BB + 1)) * kT + t] = part_rhs(C, rin, PT, J + BB + 1, t);
 #pragma unroll
     for (int c = 0; c < kT; ++c) cur[c] = nxt[c];
     lds_barrier();
+  }
+  if (PT.kind == kTop || PT.kind == kBottom) {
+    double* sr = (double*)(C.ws + WL.sepr) + (PT.kind == kBottom ? BB * kT : 0);
+    for (int i = t; i < BB * kT; i += NW * kWave) sr[i] = sh.ring[((PT.steps + i / kT) % (BB + 1)) * kT + (i % kT)];
   }
   __syncthreads();            // Y visible to every wavefront
 }
@@ -640,9 +780,20 @@ __device__ __attribute__((always_inline)) void forward_sweep(
 // order.  Thread (c = t % 16, g = t / 16) accumulates the (d, a) pairs
 // pq = g, g + NG, ... of sum_{d,a} L(J+d,J)[a][c] x_{J+d}[a] and holds one
 // element of L_JJ^{-1}; the next panel's values are loaded one step ahead.
+// Panels jhi down to jlo; blocks at rows >= nbr are absent.  rev: the bottom
+// part's reversed coordinates (panel J stored as block NB-1-J).  keep_ring:
+// the window already holds x of rows jhi+1 .. jhi+BB.  Rows are written to
+// xout (canonical order, plus addlam when given) only with write_x.
+struct BackRange {
+  int jhi, jlo, nbr;
+  bool rev, keep_ring, write_x;
+  const double* addlam;
+};
+
 template <int BB, int NW, typename R>
 __device__ __attribute__((always_inline)) void backward_sweep(
-    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* Y, double* xout) {
+    const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* Y, double* xout,
+    const BackRange& BR) {
   constexpr int NT = NW * kWave;
   constexpr int NG = NT / kT;                       // 16-thread groups
   constexpr int NPQ = (BB * kT + NG - 1) / NG;      // (d, a) pairs per thread
@@ -650,25 +801,27 @@ __device__ __attribute__((always_inline)) void backward_sweep(
   const double* Dg = (const double*)(C.ws + WL.Dg);
   const int t = threadIdx.x;
   const int cc = t & 15, grp = t >> 4;
-  for (int i = t; i < (BB + 1) * kT; i += NT) sh.ring[i] = 0.0;
+  if (!BR.keep_ring)
+    for (int i = t; i < (BB + 1) * kT; i += NT) sh.ring[i] = 0.0;
   R cur[NPQ], nxt[NPQ];
   R dcur = 0, dnxt = 0;       // element (t / 16, t % 16) of L_JJ^{-1} (t < 256)
   double ycur = 0.0, ynxt = 0.0;
   auto load = [&](int J, R* dst, R& dg, double& yv) {
-    if (J < 0) return;
-    const R* base = Lg + (size_t)J * (BB + 1) * 256;
+    if (J < BR.jlo) return;
+    const size_t sl = BR.rev ? C.NB - 1 - J : J;
+    const R* base = Lg + sl * (BB + 1) * 256;
 #pragma unroll
     for (int i = 0; i < NPQ; ++i) {
       const int pq = grp + NG * i;
       const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
-      dst[i] = (pq < BB * kT && J + d < C.NB) ? base[(size_t)d * 256 + a * kT + cc] : (R)0;
+      dst[i] = (pq < BB * kT && J + d < BR.nbr) ? base[(size_t)d * 256 + a * kT + cc] : (R)0;
     }
     if (t < 256) dg = base[t];
-    if (t < kT) yv = Y[(size_t)J * kT + t] / Dg[(size_t)J * kT + t];
+    if (t < kT) yv = Y[sl * kT + t] / Dg[sl * kT + t];
   };
-  load(C.NB - 1, cur, dcur, ycur);
+  load(BR.jhi, cur, dcur, ycur);
   lds_barrier();
-  for (int J = C.NB - 1; J >= 0; --J) {
+  for (int J = BR.jhi; J >= BR.jlo; --J) {
     load(J - 1, nxt, dnxt, ynxt);
     double s = 0.0;
 #pragma unroll
@@ -691,10 +844,11 @@ __device__ __attribute__((always_inline)) void backward_sweep(
 #pragma unroll
       for (int c2 = 0; c2 < kT; ++c2) x += sh.Xw[c2 * kLd + t] * sh.yJ[c2];   // L_JJ^{-T}
       sh.ring[(J % (BB + 1)) * kT + t] = x;
-      const int r = J * kT + t;
-      if (r < C.m) {
+      const int r = BR.rev ? C.M - 1 - (J * kT + t) : J * kT + t;
+      if (BR.write_x && r < C.m) {
         const int k = r / C.nx, px = r - k * C.nx;
-        xout[(size_t)k * C.nx + fold_x(px, C.nx)] = x;
+        const size_t c = (size_t)k * C.nx + fold_x(px, C.nx);
+        xout[c] = BR.addlam ? x + BR.addlam[c] : x;
       }
     }
 #pragma unroll
@@ -755,6 +909,8 @@ __device__ __attribute__((always_inline)) int solve_with_factor(
   const double* rvec = (const double*)(C.ws + WL.rvec);
   // the plain form refines only with a factor of an earlier iterate (stale)
   const bool plain = sizeof(R) == sizeof(double) && !stale;
+  const Part whole = make_part<BB>(C, kWhole);
+  const BackRange back{C.NB - 1, 0, C.NB, false, false, true, nullptr};
   double rn = 0.0;
   if (!plain) {
     for (int r = threadIdx.x; r < C.m; r += NW * kWave) rn = fmax(rn, fabs(rvec[r]));
@@ -762,8 +918,8 @@ __device__ __attribute__((always_inline)) int solve_with_factor(
   }
   int refines = 0;
   for (int it = 0; it <= max_refine; ++it) {
-    if (it > 0 || !have_y) forward_sweep<BB, NW, R>(C, WL, sh, rin, Y);
-    backward_sweep<BB, NW, R>(C, WL, sh, Y, it == 0 ? x : dx);
+    if (it > 0 || !have_y) forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, whole);
+    backward_sweep<BB, NW, R>(C, WL, sh, Y, it == 0 ? x : dx, back);
     if (it > 0) {
       for (int r = threadIdx.x; r < C.m; r += NW * kWave) x[r] += dx[r];
       __syncthreads();
@@ -794,6 +950,8 @@ struct BandState {
   int factor_ok;    // 1 when the stored factor was taken at the returned point
   int factored;     // a factor of S from an earlier iteration is in the workspace
   int reuse;        // this iteration's step is solved with that factor
+  int side_bad[2];  // two-sided form: a side's sweep met a non-positive pivot
+  int adj_bad;      // two-sided adjoint: its factorization met one
   double mu, uscale, h1, hinf, stinf;
 };
 static_assert(sizeof(BandState) <= 256, "state must fit the header");
@@ -912,7 +1070,8 @@ SNAP_BAND_KERNEL void band_factor(KernelArgs A) {
   }
   if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
   __syncthreads();
-  const int bad = factor_sweep<BB, NW, R>(C, WL, sh);
+  assemble_all<NW>(C, WL);
+  const int bad = factor_sweep<BB, NW, R>(C, WL, sh, make_part<BB>(C, kWhole));
   if (threadIdx.x == 0) {
     S->reuse = 0;
     S->factored = bad ? 0 : 1;
@@ -1045,49 +1204,35 @@ SNAP_BAND_KERNEL void band_finish(KernelArgs A) {
   }
 }
 
-// adjoint: S b = J W^{-1} g, grad = W^{-1}(g - J^T b), at (u*, lam*); reuses
-// the factor when the forward kept one at this point, else factors here
-template <int BB, int NW, typename R>
-SNAP_BAND_KERNEL void band_adjoint(KernelArgs A) {
-  const int sid = A.order[blockIdx.x];
-  const snap_sample_desc D = A.descs[sid];
-  __shared__ BandShared<BB, NW, R> sh;
-  const Ctx C = make_ctx(A, D, sid, true);
-  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
-  const BandState* S = (const BandState*)(C.ws + WL.hdr);
-  double* lamp = (double*)(C.ws + WL.lamp);
-  const int NT = NW * kWave;
-  const bool keep = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0;
-  const bool have = keep && S->factor_ok == 1;
-  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
-  __syncthreads();
-  int bad = 0;
-  if (have) {
-    double* rin = (double*)(C.ws + WL.rin);
-    double* rvec = (double*)(C.ws + WL.rvec);
-    for (int r = threadIdx.x; r < C.M; r += NT) {
-      double v = 0.0;
-      if (r < C.m) {
-        const int k = r / C.nx, px = r - k * C.nx, x = fold_x(px, C.nx);
-        // rhs = J W^{-1} g
-        const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
-        const double* U = C.u + (size_t)k * C.nx;
-        double s = C.g[(size_t)(k + 1) * C.nx + x] / w_at(C, k + 1, x);
-        s += C.cd * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
-        s += (C.q * U[xp] - C.c) * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
-        s += (-C.q * U[xm] - C.c) * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
-        v = s;
-        rvec[(size_t)k * C.nx + x] = s;
-      }
-      rin[r] = v;
+// adjoint right-hand side J W^{-1} g of rows [r0, r1) (internal order; rvec too)
+template <int NW>
+__device__ void adjoint_rhs_rows(const Ctx& C, const WsLayout& WL, int r0, int r1) {
+  double* rin = (double*)(C.ws + WL.rin);
+  double* rvec = (double*)(C.ws + WL.rvec);
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += NW * kWave) {
+    double v = 0.0;
+    if (r < C.m) {
+      const int k = r / C.nx, px = r - k * C.nx, x = fold_x(px, C.nx);
+      const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
+      const double* U = C.u + (size_t)k * C.nx;
+      double s = C.g[(size_t)(k + 1) * C.nx + x] / w_at(C, k + 1, x);
+      s += C.cd * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
+      s += (C.q * U[xp] - C.c) * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
+      s += (-C.q * U[xm] - C.c) * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
+      v = s;
+      rvec[(size_t)k * C.nx + x] = s;
     }
-    __syncthreads();
-  } else {
-    bad = factor_sweep<BB, NW, R>(C, WL, sh);
+    rin[r] = v;
   }
-  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, !have, lamp);
+  __syncthreads();
+}
+
+// grad = W^{-1}(g - J^T b) from b (canonical order) and the sample's statistics
+template <int NW>
+__device__ void adjoint_finish(const KernelArgs& A, const Ctx& C, const snap_sample_desc& D, int sid,
+                               const double* lamp, int bad, int refines) {
   int floored = 0;
-  for (int v = threadIdx.x; v < C.n; v += NT) {
+  for (int v = threadIdx.x; v < C.n; v += NW * kWave) {
     const int k = v / C.nx, x = v - k * C.nx;
     A.grad_uhat[D.var_off + v] = (C.g[v] - jt_at(C, lamp, k, x)) / w_at(C, k, x);
     if (k <= C.nt - 2) {
@@ -1103,6 +1248,215 @@ SNAP_BAND_KERNEL void band_adjoint(KernelArgs A) {
     st.h_inf = 0.0; st.stat_inf = 0.0;
     A.stats[sid] = st;
   }
+}
+
+// adjoint: S b = J W^{-1} g, grad = W^{-1}(g - J^T b), at (u*, lam*); reuses
+// the factor when the forward kept one at this point, else factors here
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_adjoint(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, true);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
+  double* lamp = (double*)(C.ws + WL.lamp);
+  const bool keep = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0;
+  const bool have = keep && S->factor_ok == 1;
+  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+  __syncthreads();
+  int bad = 0;
+  if (have) {
+    adjoint_rhs_rows<NW>(C, WL, 0, C.M);
+  } else {
+    assemble_all<NW>(C, WL);
+    bad = factor_sweep<BB, NW, R>(C, WL, sh, make_part<BB>(C, kWhole));
+  }
+  const int refines = solve_with_factor<BB, NW, R>(C, WL, sh, !have, lamp);
+  adjoint_finish<NW>(A, C, D, sid, lamp, bad, refines);
+}
+
+// ------------------------------------------------------------------ two-sided form
+// Kernels of the two-sided factorization (see the parts section): launches
+// marked "two per sample" run the top part in workgroup 2i and the bottom
+// part in workgroup 2i + 1 of sample order[i]; the separator kernels run one
+// workgroup per sample.  Float64 only (the plain solve needs no refinement).
+
+// rows of a side: the top assembles block rows [0, K + BB), the bottom
+// [K + BB, NB) and its own copy of the separator rows (no right-hand side)
+template <int NW>
+__device__ void assemble_part(const Ctx& C, const WsLayout& WL, const Part& P) {
+  int* acol = (int*)(C.ws + WL.acol);
+  double* aval = (double*)(C.ws + WL.aval);
+  const int s0 = P.K * kT, s1 = (C.NB - P.Kb) * kT;
+  if (P.kind == kTop) {
+    assemble_rows<NW>(C, WL, 0, s1, acol, aval, 0, true);
+  } else {
+    assemble_rows<NW>(C, WL, s1, C.M, acol, aval, 0, true);
+    assemble_rows<NW>(C, WL, s0, s1, (int*)(C.ws + WL.scol), (double*)(C.ws + WL.sval), s0, false);
+  }
+}
+
+// x = L^{-T} D^{-1} y of a two-sided factor, the rows of one side: both
+// sides first sweep the separator (the bottom keeps its rows out of xout),
+// the bottom then turns the separator's x into its reversed coordinates
+template <int BB, int NW, typename R>
+__device__ __attribute__((always_inline)) void split_backward(const Ctx& C, const WsLayout& WL,
+                                                              BandShared<BB, NW, R>& sh, int side, double* xout,
+                                                              const double* addlam) {
+  static_assert(NW * kWave >= BB * kT, "the separator's x is staged in part[]");
+  const Part PT = make_part<BB>(C, kTop);
+  const int K = PT.K, Kb = PT.Kb;
+  const double* Y = (const double*)(C.ws + WL.Y);
+  if (side == 0) {
+    backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{K + BB - 1, 0, K + BB, false, false, true, addlam});
+    return;
+  }
+  backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{K + BB - 1, K, K + BB, false, false, false, nullptr});
+  for (int i = threadIdx.x; i < BB * kT; i += NW * kWave) {
+    const int ib = i / kT, a = i - ib * kT;    // reversed local row ib, entry a
+    sh.part[i] = sh.ring[((K + BB - 1 - ib) % (BB + 1)) * kT + (15 - a)];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (BB + 1) * kT; i += NW * kWave) {
+    const int ib = i / kT, a = i - ib * kT;
+    sh.ring[((Kb + ib) % (BB + 1)) * kT + a] = ib < BB ? sh.part[i] : 0.0;
+  }
+  __syncthreads();
+  backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{Kb - 1, 0, Kb + BB, true, true, true, addlam});
+}
+
+// (two per sample) factor a side at the current (u, lam), fused forward
+// substitution, export of the side's separator update
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_factor(KernelArgs A) {
+  const int side = blockIdx.x & 1;
+  const int sid = A.order[blockIdx.x >> 1];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  if (S->phase == 2) return;
+  const Part PT = make_part<BB>(C, side ? kBottom : kTop);
+  assemble_part<NW>(C, WL, PT);
+  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+  __syncthreads();
+  const int bad = factor_sweep<BB, NW, R>(C, WL, sh, PT);
+  if (threadIdx.x == 0) S->side_bad[side] = bad;
+}
+
+// (one per sample) factor the separator; the state update of band_factor
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_sep(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  const int phase = S->phase;
+  if (phase == 2) return;
+  if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+  __syncthreads();
+  const int bad = factor_sweep<BB, NW, R>(C, WL, sh, make_part<BB>(C, kSep)) | S->side_bad[0] | S->side_bad[1];
+  if (threadIdx.x == 0) {
+    S->reuse = 0;
+    S->factored = bad ? 0 : 1;
+    if (phase == 1) {
+      S->factor_ok = bad ? 0 : 1;
+      S->phase = 2;
+    } else if (bad) {
+      S->status = SNAP_ST_SINGULAR_PIVOT;
+      S->phase = 2;
+    }
+  }
+}
+
+// (two per sample) backward substitution: lam+ = lam + dlam, a side's rows
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_solve(KernelArgs A) {
+  const int side = blockIdx.x & 1;
+  const int sid = A.order[blockIdx.x >> 1];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0) return;
+  split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.lamp), C.lam);
+}
+
+// adjoint, (two per sample): a side's right-hand side and forward
+// substitution with the kept factor, or a side's factorization
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_adj1(KernelArgs A) {
+  const int side = blockIdx.x & 1;
+  const int sid = A.order[blockIdx.x >> 1];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, true);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  const bool have = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0 && S->factor_ok == 1;
+  const Part PT = make_part<BB>(C, side ? kBottom : kTop);
+  if (have) {
+    const int s1 = (C.NB - PT.Kb) * kT;
+    adjoint_rhs_rows<NW>(C, WL, side ? s1 : 0, side ? C.M : s1);
+    forward_sweep<BB, NW, R>(C, WL, sh, (const double*)(C.ws + WL.rin), (double*)(C.ws + WL.Y), PT);
+  } else {
+    assemble_part<NW>(C, WL, PT);
+    if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+    __syncthreads();
+    const int bad = factor_sweep<BB, NW, R>(C, WL, sh, PT);
+    if (threadIdx.x == 0) S->side_bad[side] = bad;
+  }
+}
+
+// adjoint, (one per sample): the separator's forward substitution, or its
+// factorization
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_adj2(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, true);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  const bool have = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0 && S->factor_ok == 1;
+  if (have) {
+    forward_sweep<BB, NW, R>(C, WL, sh, (const double*)(C.ws + WL.rin), (double*)(C.ws + WL.Y),
+                             make_part<BB>(C, kSep));
+  } else {
+    if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
+    __syncthreads();
+    const int bad = factor_sweep<BB, NW, R>(C, WL, sh, make_part<BB>(C, kSep)) | S->side_bad[0] | S->side_bad[1];
+    if (threadIdx.x == 0) S->adj_bad = bad;
+  }
+}
+
+// adjoint, (two per sample): backward substitution, a side's rows of b
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_adj3(KernelArgs A) {
+  const int side = blockIdx.x & 1;
+  const int sid = A.order[blockIdx.x >> 1];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, true);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.lamp), nullptr);
+}
+
+// adjoint, (one per sample): the gradient and the statistics
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_adj4(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  const Ctx C = make_ctx(A, D, sid, true);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
+  const bool have = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0 && S->factor_ok == 1;
+  adjoint_finish<NW>(A, C, D, sid, (const double*)(C.ws + WL.lamp), have ? 0 : S->adj_bad, 0);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -1144,9 +1498,56 @@ static void launch_band(const KernelArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((band_finish<BB, NW, R>), grid, block, 0, st, a);
 }
 
+// the two-sided form: the same Newton loop with each factorization and
+// backward substitution split over two workgroups per sample (see the parts
+// section) and the separator's factorization in a launch of its own
+template <int BB, int NW>
+static void launch_band_split(const KernelArgs& a, hipStream_t st) {
+  using R = double;
+  const dim3 one(a.count), two(2 * a.count), block(NW * kWave);
+  if (a.backward) {
+    hipLaunchKernelGGL((band_split_adj1<BB, NW, R>), two, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_adj2<BB, NW, R>), one, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_adj3<BB, NW, R>), two, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_adj4<BB, NW, R>), one, block, 0, st, a);
+    return;
+  }
+  hipLaunchKernelGGL((band_init<BB, NW, R>), one, block, 0, st, a);
+  hipLaunchKernelGGL((band_eval<BB, NW, R>), one, block, 0, st, a);
+  KernelTimer* tm = tl_timer;
+  for (int it = 0; it < a.opt.max_newton; ++it) {
+    if (tm) timer_mark(tm, kTimedBandFactor, st);
+    hipLaunchKernelGGL((band_split_factor<BB, NW, R>), two, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_sep<BB, NW, R>), one, block, 0, st, a);
+    if (tm) timer_mark(tm, kTimedBandFactor, st);
+    if (tm) timer_mark(tm, kTimedBandSolve, st);
+    hipLaunchKernelGGL((band_split_solve<BB, NW, R>), two, block, 0, st, a);
+    if (tm) timer_mark(tm, kTimedBandSolve, st);
+    hipLaunchKernelGGL((band_step<BB, NW, R>), one, block, 0, st, a);
+    hipLaunchKernelGGL((band_eval<BB, NW, R>), one, block, 0, st, a);
+  }
+  if (a.opt.flags & SNAP_FLAG_KEEP_FACTOR) {
+    hipLaunchKernelGGL((band_split_factor<BB, NW, R>), two, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_sep<BB, NW, R>), one, block, 0, st, a);
+  }
+  hipLaunchKernelGGL((band_finish<BB, NW, R>), one, block, 0, st, a);
+}
+
 // class = BB + kBandAlt * alt: alt 0 is the default launch shape (four
-// wavefronts for BB <= 9, eight above), alt 1 the alternative (eight, BB <= 9)
+// wavefronts for BB <= 9, eight above), alt 1 the alternative (eight, BB <= 9),
+// alt 2 the two-sided form (BB >= 13, float64)
 constexpr int kBandAlt = 32;
+constexpr int kBandSplit = 2 * kBandAlt;
+
+// The two-sided form halves a factorization's chain of panel steps at the
+// cost of a third launch (the separator, BB panel steps) and twice the
+// workgroups; it is the default where the chain is long (wide bands, at least
+// 40 BB block rows) and the factors are float64 (the mixed form's refinement
+// sweeps are one-sided).
+static bool split_pays(int nx, int nt, int bb, bool mixed) {
+  const int64_t m = (int64_t)nx * (nt - 1), nb = (m + kT - 1) / kT;
+  return !mixed && bb >= 13 && nb >= 40 * bb;
+}
 
 template <typename R>
 static int launch_bb(int cls, const KernelArgs& a, hipStream_t st) {
@@ -1180,6 +1581,12 @@ static int launch_bb(int cls, const KernelArgs& a, hipStream_t st) {
       case 9: launch_band<9, 8, R>(a, st); break;
       default: return SNAP_EUNSUPPORTED;
     }
+  } else if (alt == 2 && std::is_same<R, double>::value) {
+    switch (bb) {
+      case 13: launch_band_split<13, 8>(a, st); break;
+      case 17: launch_band_split<17, 8>(a, st); break;
+      default: return SNAP_EUNSUPPORTED;
+    }
   } else {
     return SNAP_EUNSUPPORTED;
   }
@@ -1192,22 +1599,40 @@ bool band_supported(int nx, int nt, bool mixed) {
   return nx >= 3 && nt >= 2 && pick_bb(band_bb(nx, nt)) > 0 && (int64_t)nx * nt < (1 << 30);
 }
 
-// Kernel class of a shape: the instantiated block half-bandwidth, default
-// launch shape.
-int band_class(int nx, int nt) { return band_supported(nx, nt, false) ? pick_bb(band_bb(nx, nt)) : -1; }
+// Kernel class of a shape: the instantiated block half-bandwidth with the
+// default launch shape, or its two-sided form where that pays.
+int band_class(int nx, int nt, bool mixed) {
+  if (!band_supported(nx, nt, mixed)) return -1;
+  const int bb = pick_bb(band_bb(nx, nt));
+  return split_pays(nx, nt, bb, mixed) ? bb + kBandSplit : bb;
+}
 
-// Classes the autotuner may choose between for a class (default shape first).
-int band_variants(int cls, int* out, int cap) {
-  int n = 0;
+// Classes the autotuner may choose between for a shape (default first): the
+// other launch shape at BB <= 9; the one- or two-sided form above (the
+// two-sided one where its parts have at least BB block rows each).
+int band_variants(int nx, int nt, bool mixed, int* out, int cap) {
+  const int cls = band_class(nx, nt, mixed);
   if (cls < 0 || cap < 1) return 0;
-  cls %= kBandAlt;
+  const int bb = cls % kBandAlt;
+  const int64_t nb = ((int64_t)nx * (nt - 1) + kT - 1) / kT;
+  int n = 0;
   out[n++] = cls;
-  if (cls <= 9 && n < cap) out[n++] = cls + kBandAlt;
+  if (n >= cap) return n;
+  if (bb <= 9) {
+    out[n++] = bb + kBandAlt;
+  } else if (cls != bb) {
+    out[n++] = bb;
+  } else if (!mixed && nb >= 3 * bb) {
+    out[n++] = bb + kBandSplit;
+  }
   return n;
 }
 
 // wavefronts per workgroup of a class (for plan descriptions)
 int band_waves(int cls) { return (cls % kBandAlt) <= 9 && cls / kBandAlt == 0 ? 4 : 8; }
+
+// workgroups per sample of a class's factorization
+int band_sides(int cls) { return cls / kBandAlt == 2 ? 2 : 1; }
 
 size_t band_workspace_bytes(int nx, int nt, bool mixed) {  // the same for every launch shape
   const int bb = pick_bb(band_bb(nx, nt));

@@ -9,8 +9,8 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def gpu_project(batch, options=None):
-    plan = snap.Plan.from_batch(batch, options or snap.Options())
+def gpu_project(batch, options=None, plan=None):
+    plan = plan or snap.Plan.from_batch(batch, options or snap.Options())
     uhat = to_dev(batch.uhat)
     aux = to_dev(batch.aux)
     u, lam, st, ws = snap.project(plan, uhat, aux)
