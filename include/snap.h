@@ -110,13 +110,16 @@ enum snap_flags {
                                 shape changes the summation order of some
                                 reductions, so results may differ from the
                                 untuned plan's in the last bits. */
-  SNAP_FLAG_SOC = 8          /* slab-row families: when the full Newton step
-                                fails the merit test and raised the constraint
-                                violation, try one second-order correction
-                                q = p - W^{-1} J^T S^{-1} h(u + p) with the factor
-                                at u before halving.  Off by default: on strongly
-                                nonlinear Fisher-KPP samples it slowed or stalled
-                                convergence where plain backtracking did not. */
+  SNAP_FLAG_SOC = 8          /* slab-row and banded families: when the full
+                                Newton step fails the merit test and raised the
+                                constraint violation, try one second-order
+                                correction q = p - W^{-1} J^T S^{-1} h(u + p) with
+                                the factor at u before halving (banded family:
+                                one more launch per Newton iteration, which
+                                returns at once unless a correction is due).
+                                Off by default: on strongly nonlinear Fisher-KPP
+                                samples it slowed or stalled convergence where
+                                plain backtracking did not. */
 };
 
 /* call-level return codes */

@@ -108,7 +108,7 @@ struct Ctx {
 
 // workspace layout of one sample (byte offsets, 256-aligned)
 struct WsLayout {
-  size_t hdr, L, Dg, Y, rin, rvec, lamp, p, t, res, acol, aval;
+  size_t hdr, L, Dg, Y, rin, rvec, lamp, p, t, res, z, acol, aval;
   size_t scol, sval, sepw, sepr;   // two-sided form: separator rows, exported updates
   size_t total;
 };
@@ -138,6 +138,7 @@ __host__ __device__ inline WsLayout ws_layout(int nx, int nt, int BB, size_t rsi
   w.p = o; o += align256(n * 8);
   w.t = o; o += align256(n * 8);
   w.res = o; o += align256(m * 8);
+  w.z = o; o += align256(m * 8);        // second-order correction: S z = h(u + p)
   w.acol = o; o += align256(M * kContrib * 4);
   w.aval = o; o += align256(M * kContrib * 8);
   // two-sided form: the bottom sweep's copy of the separator rows' stencil
@@ -952,6 +953,8 @@ struct BandState {
   int reuse;        // this iteration's step is solved with that factor
   int side_bad[2];  // two-sided form: a side's sweep met a non-positive pivot
   int adj_bad;      // two-sided adjoint: its factorization met one
+  int soc_try;      // the full step failed and raised ||h||_1: band_soc tries a correction
+  double soc_dd, soc_pp;   // (u - u_hat).p and p.p of that step
   double mu, uscale, h1, hinf, stinf;
 };
 static_assert(sizeof(BandState) <= 256, "state must fit the header");
@@ -1110,6 +1113,88 @@ SNAP_BAND_KERNEL void band_solve(KernelArgs A) {
   if (threadIdx.x == 0) S->refines += refines;
 }
 
+// x = L^{-T} D^{-1} y of a two-sided factor, the rows of one side: both
+// sides first sweep the separator (the bottom keeps its rows out of xout),
+// the bottom then turns the separator's x into its reversed coordinates
+template <int BB, int NW, typename R>
+__device__ __attribute__((always_inline)) void split_backward(const Ctx& C, const WsLayout& WL,
+                                                              BandShared<BB, NW, R>& sh, int side, double* xout,
+                                                              const double* addlam) {
+  static_assert(NW * kWave >= BB * kT, "the separator's x is staged in part[]");
+  const Part PT = make_part<BB>(C, kTop);
+  const int K = PT.K, Kb = PT.Kb;
+  const double* Y = (const double*)(C.ws + WL.Y);
+  if (side == 0) {
+    backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{K + BB - 1, 0, K + BB, false, false, true, addlam});
+    return;
+  }
+  backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{K + BB - 1, K, K + BB, false, false, false, nullptr});
+  for (int i = threadIdx.x; i < BB * kT; i += NW * kWave) {
+    const int ib = i / kT, a = i - ib * kT;    // reversed local row ib, entry a
+    sh.part[i] = sh.ring[((K + BB - 1 - ib) % (BB + 1)) * kT + (15 - a)];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (BB + 1) * kT; i += NW * kWave) {
+    const int ib = i / kT, a = i - ib * kT;
+    sh.ring[((Kb + ib) % (BB + 1)) * kT + a] = ib < BB ? sh.part[i] : 0.0;
+  }
+  __syncthreads();
+  backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{Kb - 1, 0, Kb + BB, true, true, true, addlam});
+}
+
+// h of row (k, x) at u + alpha p
+__device__ __forceinline__ double h_trial(const Ctx& C, const double* pv, double alpha, int k, int x) {
+  const size_t b0 = (size_t)k * C.nx;
+  const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
+  const double u0 = C.u[b0 + x] + alpha * pv[b0 + x];
+  const double up = C.u[b0 + xp] + alpha * pv[b0 + xp];
+  const double um = C.u[b0 + xm] + alpha * pv[b0 + xm];
+  const double un = C.u[b0 + C.nx + x] + alpha * pv[b0 + C.nx + x];
+  return un - u0 + 0.5 * C.q * (up * up - um * um) - C.c * (up - 2.0 * u0 + um);
+}
+
+// ||h||_1 at u + alpha p
+template <int NW>
+__device__ double h1_trial(const Ctx& C, const double* pv, double alpha, double (*red)[4]) {
+  double ht = 0.0;
+  for (int r = threadIdx.x; r < C.m; r += NW * kWave) {
+    const int k = r / C.nx, x = r - k * C.nx;
+    ht += fabs(h_trial(C, pv, alpha, k, x));
+  }
+  return block_sum<NW>(ht, red, 1);
+}
+
+// Armijo backtracking of the l1 merit phi = 1/2||u - u_hat||^2 + mu ||h||_1
+// along p: trial steps alpha, alpha/2, ... (ntries of them).  Its change is
+// formed from differences (alpha d.p + alpha^2/2 p.p + mu (||h_t||_1 -
+// ||h||_1)), never from phi values themselves, so rounding of the large sums
+// cancels.  Returns the accepted step, or 0; counts the rejected trials.
+// With soc_stop, a rejected full step that raised ||h||_1 stops the search
+// (soc is set) for a second-order correction.
+template <int NW>
+__device__ double merit_search(const Ctx& C, const double* pv, double dd, double pp, double mu, double h1,
+                               double hinf, double alpha, int ntries, double (*red)[4], int& backtracks,
+                               bool soc_stop, bool& soc) {
+  const double dphi = dd - mu * h1;
+  soc = false;
+  for (int i = 0; i < ntries; ++i) {
+    const double ht = h1_trial<NW>(C, pv, alpha, red);
+    const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (ht - h1);
+    // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
+    // ||h||_1 along p sits below the rounding of the row sums
+    // (with W >= 0.1 the step is a descent direction of the merit unless it
+    // is zero; a zero step is taken, any other step must pass the test)
+    if (dphi_t <= 1e-4 * alpha * dphi || !(pp > 0.0) || hinf <= 1e-6) return alpha;
+    ++backtracks;
+    if (i == 0 && soc_stop && ht > h1) {
+      soc = true;
+      return 0.0;
+    }
+    alpha *= 0.5;
+  }
+  return 0.0;
+}
+
 // step p = -W^{-1}(u - u_hat + J^T lam+), l1-merit backtracking, update
 template <int BB, int NW, typename R>
 SNAP_BAND_KERNEL void band_step(KernelArgs A) {
@@ -1138,36 +1223,23 @@ SNAP_BAND_KERNEL void band_step(KernelArgs A) {
   lmax = block_max<NW>(lmax, red, 1);
   const double h1 = S->h1, hinf = S->hinf;
   const double mu = fmax(S->mu, 1.1 * lmax + 1e-8);
-  // merit phi = 1/2||u - u_hat||^2 + mu ||h||_1; its change along p is formed
-  // from differences (alpha d.p + alpha^2/2 p.p + mu (||h_t||_1 - ||h||_1)),
-  // never from phi values themselves, so rounding of the large sums cancels
-  const double dphi = dd - mu * h1;
-  double alpha = 1.0;
-  int ok = 0, backtracks = 0;
-  for (int ls = 0; ls <= A.opt.max_ls; ++ls) {
-    double ht = 0.0;
-    for (int v = threadIdx.x; v < C.n; v += NT) {
-      const int k = v / C.nx, x = v - k * C.nx;
-      if (k <= C.nt - 2) {
-        const size_t b0 = (size_t)k * C.nx;
-        const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
-        const double u0 = C.u[b0 + x] + alpha * pv[b0 + x];
-        const double up = C.u[b0 + xp] + alpha * pv[b0 + xp];
-        const double um = C.u[b0 + xm] + alpha * pv[b0 + xm];
-        const double un = C.u[b0 + C.nx + x] + alpha * pv[b0 + C.nx + x];
-        ht += fabs(un - u0 + 0.5 * C.q * (up * up - um * um) - C.c * (up - 2.0 * u0 + um));
-      }
+  int backtracks = 0;
+  bool soc = false;
+  const bool soc_on = (A.opt.flags & SNAP_FLAG_SOC) != 0;
+  const double alpha =
+      merit_search<NW>(C, pv, dd, pp, mu, h1, hinf, 1.0, A.opt.max_ls + 1, red, backtracks, soc_on, soc);
+  if (soc) {
+    // band_soc tries u + p + p_soc, then halves along p
+    if (threadIdx.x == 0) {
+      S->mu = mu;
+      S->backtracks += backtracks;
+      S->soc_try = 1;
+      S->soc_dd = dd;
+      S->soc_pp = pp;
     }
-    ht = block_sum<NW>(ht, red, 1);
-    const double dphi_t = alpha * dd + 0.5 * alpha * alpha * pp + mu * (ht - h1);
-    // local phase (||h||_inf <= 1e-6): full Newton steps; there the change of
-    // ||h||_1 along p sits below the rounding of the row sums
-    // (with W >= 0.1 the step is a descent direction of the merit unless it
-    // is zero; a zero step is taken, any other step must pass the test)
-    if (dphi_t <= 1e-4 * alpha * dphi || !(pp > 0.0) || hinf <= 1e-6) { ok = 1; break; }
-    alpha *= 0.5;
-    ++backtracks;
+    return;
   }
+  const int ok = alpha > 0.0;
   if (ok) {
     for (int v = threadIdx.x; v < C.n; v += NT) C.u[v] += alpha * pv[v];
     for (int r = threadIdx.x; r < C.m; r += NT) C.lam[r] += alpha * (lamp[r] - C.lam[r]);
@@ -1175,7 +1247,88 @@ SNAP_BAND_KERNEL void band_step(KernelArgs A) {
   if (threadIdx.x == 0) {
     S->mu = mu;
     S->backtracks += backtracks;
+    S->soc_try = 0;
     if (ok) {
+      S->iters += 1;
+    } else {
+      S->status = SNAP_ST_LS_FAIL;
+      S->phase = 2;
+    }
+  }
+}
+
+// Second-order correction (SNAP_FLAG_SOC), after band_step rejected the full
+// step and it raised ||h||_1: with the step's factor (one- or two-sided,
+// swept here by one workgroup), solve S z = h(u + p) and try
+// u + q, q = p - W^{-1} J^T z, under the same Armijo test (the directional
+// derivative of p); if it fails, halve along p from alpha = 1/2.
+template <int BB, int NW, typename R, bool SPLIT>
+SNAP_BAND_KERNEL void band_soc(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0 || !S->soc_try) return;
+  const int NT = NW * kWave;
+  const double* pv = (const double*)(C.ws + WL.p);
+  const double* lamp = (const double*)(C.ws + WL.lamp);
+  double* rin = (double*)(C.ws + WL.rin);
+  double* rvec = (double*)(C.ws + WL.rvec);
+  double* z = (double*)(C.ws + WL.z);
+  double* qv = (double*)(C.ws + WL.t);
+  for (int r = threadIdx.x; r < C.M; r += NT) {
+    double v = 0.0;
+    if (r < C.m) {
+      const int k = r / C.nx, px = r - k * C.nx, x = fold_x(px, C.nx);
+      v = h_trial(C, pv, 1.0, k, x);
+      rvec[(size_t)k * C.nx + x] = v;
+    }
+    rin[r] = v;
+  }
+  __syncthreads();
+  if constexpr (SPLIT) {
+    double* Y = (double*)(C.ws + WL.Y);
+    forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kTop));
+    forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kBottom));
+    forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kSep));
+    split_backward<BB, NW, R>(C, WL, sh, 0, z, nullptr);
+    split_backward<BB, NW, R>(C, WL, sh, 1, z, nullptr);
+  } else {
+    (void)solve_with_factor<BB, NW, R>(C, WL, sh, false, z, 6, 0.1 * A.opt.tol_h, false);
+  }
+  double dq = 0.0, qq = 0.0;
+  for (int v = threadIdx.x; v < C.n; v += NT) {
+    const int k = v / C.nx, x = v - k * C.nx;
+    const double q = pv[v] - jt_at(C, z, k, x) / w_at(C, k, x);
+    qv[v] = q;
+    dq += dres(C, v) * q;
+    qq += q * q;
+  }
+  dq = block_sum<NW>(dq, sh.red, 0);
+  qq = block_sum<NW>(qq, sh.red, 2);
+  const double mu = S->mu, h1 = S->h1, hinf = S->hinf, dd = S->soc_dd, pp = S->soc_pp;
+  const double ht = h1_trial<NW>(C, qv, 1.0, sh.red);
+  int backtracks = 0, taken = 0;
+  double alpha = 0.0;
+  if (dq + 0.5 * qq + mu * (ht - h1) <= 1e-4 * (dd - mu * h1)) {
+    for (int v = threadIdx.x; v < C.n; v += NT) C.u[v] += qv[v];
+    for (int r = threadIdx.x; r < C.m; r += NT) C.lam[r] = lamp[r];
+    taken = 1;
+  } else {
+    bool soc = false;
+    alpha = merit_search<NW>(C, pv, dd, pp, mu, h1, hinf, 0.5, A.opt.max_ls, sh.red, backtracks, false, soc);
+    if (alpha > 0.0) {
+      for (int v = threadIdx.x; v < C.n; v += NT) C.u[v] += alpha * pv[v];
+      for (int r = threadIdx.x; r < C.m; r += NT) C.lam[r] += alpha * (lamp[r] - C.lam[r]);
+      taken = 1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    S->soc_try = 0;
+    S->backtracks += backtracks;
+    if (taken) {
       S->iters += 1;
     } else {
       S->status = SNAP_ST_LS_FAIL;
@@ -1295,35 +1448,6 @@ __device__ void assemble_part(const Ctx& C, const WsLayout& WL, const Part& P) {
     assemble_rows<NW>(C, WL, s1, C.M, acol, aval, 0, true);
     assemble_rows<NW>(C, WL, s0, s1, (int*)(C.ws + WL.scol), (double*)(C.ws + WL.sval), s0, false);
   }
-}
-
-// x = L^{-T} D^{-1} y of a two-sided factor, the rows of one side: both
-// sides first sweep the separator (the bottom keeps its rows out of xout),
-// the bottom then turns the separator's x into its reversed coordinates
-template <int BB, int NW, typename R>
-__device__ __attribute__((always_inline)) void split_backward(const Ctx& C, const WsLayout& WL,
-                                                              BandShared<BB, NW, R>& sh, int side, double* xout,
-                                                              const double* addlam) {
-  static_assert(NW * kWave >= BB * kT, "the separator's x is staged in part[]");
-  const Part PT = make_part<BB>(C, kTop);
-  const int K = PT.K, Kb = PT.Kb;
-  const double* Y = (const double*)(C.ws + WL.Y);
-  if (side == 0) {
-    backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{K + BB - 1, 0, K + BB, false, false, true, addlam});
-    return;
-  }
-  backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{K + BB - 1, K, K + BB, false, false, false, nullptr});
-  for (int i = threadIdx.x; i < BB * kT; i += NW * kWave) {
-    const int ib = i / kT, a = i - ib * kT;    // reversed local row ib, entry a
-    sh.part[i] = sh.ring[((K + BB - 1 - ib) % (BB + 1)) * kT + (15 - a)];
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < (BB + 1) * kT; i += NW * kWave) {
-    const int ib = i / kT, a = i - ib * kT;
-    sh.ring[((Kb + ib) % (BB + 1)) * kT + a] = ib < BB ? sh.part[i] : 0.0;
-  }
-  __syncthreads();
-  backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{Kb - 1, 0, Kb + BB, true, true, true, addlam});
 }
 
 // (two per sample) factor a side at the current (u, lam), fused forward
@@ -1490,6 +1614,7 @@ static void launch_band(const KernelArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((band_solve<BB, NW, R>), grid, block, 0, st, a);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_step<BB, NW, R>), grid, block, 0, st, a);
+    if (a.opt.flags & SNAP_FLAG_SOC) hipLaunchKernelGGL((band_soc<BB, NW, R, false>), grid, block, 0, st, a);
     hipLaunchKernelGGL((band_eval<BB, NW, R>), grid, block, 0, st, a);
   }
   // the final factor of a sample that converged at the last evaluation
@@ -1524,6 +1649,7 @@ static void launch_band_split(const KernelArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((band_split_solve<BB, NW, R>), two, block, 0, st, a);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_step<BB, NW, R>), one, block, 0, st, a);
+    if (a.opt.flags & SNAP_FLAG_SOC) hipLaunchKernelGGL((band_soc<BB, NW, R, true>), one, block, 0, st, a);
     hipLaunchKernelGGL((band_eval<BB, NW, R>), one, block, 0, st, a);
   }
   if (a.opt.flags & SNAP_FLAG_KEEP_FACTOR) {

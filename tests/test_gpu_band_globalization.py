@@ -89,3 +89,31 @@ def test_noisy_burgers_two_sided():
     plan.set_group_class(0, 64 + 13)
     res = gpu_project(b, plan=plan)
     _check(b, res, 1e-10, 1e-8)
+
+
+@pytest.mark.parametrize("precision,tol,lam_tol", [(snap.PREC_FP64, 1e-10, 1e-8),
+                                                   (snap.PREC_MIXED, 1e-6, 1e-4)])
+def test_noisy_burgers_second_order_correction(precision, tol, lam_tol):
+    # SNAP_FLAG_SOC: band_soc solves S z = h(u + p) with the step's factor and
+    # tries u + p - W^{-1} J^T z before halving.  Every sample still
+    # converges to a valid point, and the correction changes the iteration on
+    # some sample (the path ran)
+    changed = 0
+    for nx, nt, dt, amp in CASES:
+        b = _noisy(nx, nt, dt, amp)
+        plain = gpu_project(b, snap.Options(precision=precision, max_newton=100))
+        res = gpu_project(b, snap.Options(precision=precision, max_newton=100, flags=snap.FLAG_SOC))
+        print("soc newton iters", res["stats"]["newton_iters"].tolist(),
+              "plain", plain["stats"]["newton_iters"].tolist())
+        _check(b, res, tol, lam_tol)
+        changed += int((res["stats"]["newton_iters"] != plain["stats"]["newton_iters"]).sum())
+    assert changed > 0
+
+
+def test_noisy_burgers_second_order_correction_two_sided():
+    b = _noisy(192, 5, 0.003, 3.0)
+    plan = snap.Plan.from_batch(b, snap.Options(max_newton=100, flags=snap.FLAG_SOC))
+    plan.set_group_class(0, 64 + 13)
+    res = gpu_project(b, plan=plan)
+    _check(b, res, 1e-10, 1e-8)
+    print("two-sided soc newton iters", res["stats"]["newton_iters"].tolist())
