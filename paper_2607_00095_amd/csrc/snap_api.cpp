@@ -29,6 +29,7 @@ int band_variants(int nx, int nt, bool mixed, int* out, int cap);
 int slab_waves(int cls);
 int band_waves(int cls);
 int band_sides(int cls);
+int band_group_class(int cls, int min_nb, int count, int ncu, bool mixed);
 bool spec_supported(int nx, int ny, int nt);
 size_t spec_workspace_bytes(int nx, int nt);
 int spec_launch(const KernelArgs& a, hipStream_t st);
@@ -422,6 +423,21 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
     p->groups[gi].cost += cost[s];
   }
   p->ws_bytes = std::max<size_t>(ws, 256);
+  // banded groups smaller than the machine: the launch shape by group size
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
+    free_plan(p);
+    return SNAP_EHIP;
+  }
+  for (auto& g : p->groups) {
+    if (g.kind != 1) continue;
+    int min_nb = INT32_MAX;
+    for (int32_t id : g.ids) {
+      const snap_sample_desc& d = p->descs[id];
+      min_nb = std::min<int>(min_nb, (int)(((int64_t)d.nx * (d.nt - 1) + 15) / 16));
+    }
+    g.cls = band_group_class(g.cls, min_nb, (int)g.ids.size(), ncu, mixed);
+  }
   // longest samples first inside a group; most expensive groups first
   for (auto& g : p->groups)
     std::stable_sort(g.ids.begin(), g.ids.end(),

@@ -1760,6 +1760,19 @@ int band_waves(int cls) { return (cls % kBandAlt) <= 9 && cls / kBandAlt == 0 ? 
 // workgroups per sample of a class's factorization
 int band_sides(int cls) { return cls / kBandAlt == 2 ? 2 : 1; }
 
+// The default class of a whole group: a group that leaves CUs idle (at most
+// one sample per CU) takes the shape that puts more of a CU on each sample,
+// eight wavefronts at BB <= 9, the two-sided factorization at BB >= 13
+// (float64; every sample's parts at least BB block rows).  min_nb is the
+// fewest block rows of the group's samples.
+int band_group_class(int cls, int min_nb, int count, int ncu, bool mixed) {
+  const int bb = cls % kBandAlt;
+  if (cls / kBandAlt != 0 || count > ncu) return cls;
+  if (bb <= 9) return bb + kBandAlt;
+  if (!mixed && min_nb >= 3 * bb) return bb + kBandSplit;
+  return cls;
+}
+
 size_t band_workspace_bytes(int nx, int nt, bool mixed) {  // the same for every launch shape
   const int bb = pick_bb(band_bb(nx, nt));
   return ws_layout(nx, nt, bb, mixed ? sizeof(float) : sizeof(double)).total;

@@ -93,29 +93,34 @@ def test_burgers_mixed_full_config_sampled():
 
 
 # Every band class of the ragged workload: Nx = 64 / 96 / 128 / 192 / 256 give
-# block bandwidths BB = 5 / 7 / 9 / 13 / 17 (the last two on the 8-wavefront
-# default).  Short time spans keep the oracle within seconds.
+# block bandwidths BB = 5 / 7 / 9 / 13 / 17.  Each shape runs with every
+# launch shape its group offers (one-sided 4 or 8 wavefronts, two-sided).
+# Short time spans keep the oracle within seconds.
 WIDE = [(96, 6), (192, 5), (256, 4), (96, 33), (256, 9)]
 
 
 @pytest.mark.parametrize("nx,nt", WIDE)
 @pytest.mark.parametrize("prec", [snap.PREC_FP64, snap.PREC_MIXED])
 def test_burgers_every_band_class(nx, nt, prec):
-    from gpu_helpers import check_samples
+    from gpu_helpers import check_samples, oracle_solution
     dt = 1e-3 * min(1.0, (128.0 / nx) ** 2)
     b = synthgen.burgers_batch(batch=2, nx=nx, nt=nt, dt=dt, seed=9 * nx + nt)
-    res = gpu_project(b, snap.Options(precision=prec, flags=snap.FLAG_KEEP_FACTOR))
+    opts = snap.Options(precision=prec, flags=snap.FLAG_KEEP_FACTOR)
     fp64 = prec == snap.PREC_FP64
-    check_samples(b, res, [0, 1], 1e-10 if fp64 else 1e-6, 1e-8 if fp64 else 1e-4)
     grad = synthgen.upstream_grad(b, seed=nx)
-    g, st = gpu_backward(res, grad)
-    assert (st["status"] == 0).all()
-    from gpu_helpers import oracle_solution
-    for s, smp in enumerate(b.samples):
-        vo = b.var_off[s]
-        u_o, lam_o = oracle_solution(smp)
-        g_o = adjoint_sample(family_of(smp), u_o, lam_o, grad[vo:vo + smp.n])
-        assert rel_err(g[vo:vo + smp.n], g_o) <= (1e-10 if fp64 else 1e-6), (s, rel_err(g[vo:vo + smp.n], g_o))
+    for cls in snap.Plan.from_batch(b, opts).group_classes(0):
+        plan = snap.Plan.from_batch(b, opts)
+        plan.set_group_class(0, cls)
+        res = gpu_project(b, plan=plan)
+        check_samples(b, res, [0, 1], 1e-10 if fp64 else 1e-6, 1e-8 if fp64 else 1e-4)
+        g, st = gpu_backward(res, grad)
+        assert (st["status"] == 0).all()
+        for s, smp in enumerate(b.samples):
+            vo = b.var_off[s]
+            u_o, lam_o = oracle_solution(smp)
+            g_o = adjoint_sample(family_of(smp), u_o, lam_o, grad[vo:vo + smp.n])
+            assert rel_err(g[vo:vo + smp.n], g_o) <= (1e-10 if fp64 else 1e-6), \
+                (cls, s, rel_err(g[vo:vo + smp.n], g_o))
 
 
 @pytest.mark.parametrize("prec", [snap.PREC_FP64, snap.PREC_MIXED])

@@ -69,6 +69,17 @@ def test_two_sided_matches_oracle(nx, nt, keep):
     _check_adjoint(b, res, synthgen.upstream_grad(b, seed=nx + nt), 1e-10)
 
 
+def test_small_groups_take_the_wider_shapes():
+    # at most one sample per CU: two-sided at BB >= 13, 8 wavefronts at BB <= 9;
+    # a group larger than the machine keeps the one-sided 4-wavefront default
+    small = snap.Plan.from_batch(synthgen.burgers_batch(batch=4, nx=192, nt=9, dt=_dt(192), seed=1))
+    assert "two-sided" in small.describe()
+    b9 = snap.Plan.from_batch(synthgen.burgers_batch(batch=4, nx=128, nt=9, seed=1))
+    assert "class 41, 8 wavefronts" in b9.describe(), b9.describe()
+    big = snap.Plan.from_batch(synthgen.burgers_batch(batch=300, nx=128, nt=3, seed=1))
+    assert "class 9, 4 wavefronts" in big.describe(), big.describe()
+
+
 @pytest.mark.parametrize("nx,nt", [(192, 48), (256, 45)])
 def test_two_sided_is_the_default_on_long_wide_bands(nx, nt):
     # 564 and 704 block rows: at least 40 BB, where the form is the default
@@ -85,7 +96,9 @@ def test_two_sided_agrees_with_one_sided(nx, nt):
     # iterates agree to rounding, the iteration counts exactly
     b = synthgen.burgers_batch(batch=3, nx=nx, nt=nt, dt=_dt(nx), seed=nx + 7 * nt)
     opts = snap.Options(flags=snap.FLAG_KEEP_FACTOR)
-    one = gpu_project(b, opts)
+    plan_one = snap.Plan.from_batch(b, opts)
+    plan_one.set_group_class(0, _band_bb(nx))
+    one = gpu_project(b, plan=plan_one)
     assert "two-sided" not in one["plan"].describe()
     two = gpu_project(b, plan=_forced(b, opts))
     np.testing.assert_array_equal(one["stats"]["newton_iters"], two["stats"]["newton_iters"])
