@@ -259,12 +259,12 @@ int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed);
  * the one in use first; *count receives how many there are (at most cap are
  * written).  Groups are numbered as in snap_plan_describe.  Banded family:
  * class BB (block half-bandwidth, default shape), BB + 32 (the other
- * wavefront count, BB <= 9), BB + 64 (two-sided factorization, float64,
- * BB >= 13: two workgroups per sample factor the band from both ends toward
- * a separator, which halves the chain of dependent panel steps; the default
+ * wavefront count, BB <= 9), BB + 64 (two-sided factorization, BB >= 13:
+ * two workgroups per sample factor the band from both ends toward a
+ * separator, which halves the chain of dependent panel steps; the default
  * for bands of at least 40 BB block rows).  A banded group of at most one
  * sample per CU defaults to BB + 32 at BB <= 9 and to BB + 64 at BB >= 13
- * (FP64, at least 3 BB block rows per sample). */
+ * (at least 3 BB block rows per sample). */
 int snap_plan_group_classes(snap_plan plan, int32_t group, int32_t* classes, int32_t cap,
                             int32_t* count);
 

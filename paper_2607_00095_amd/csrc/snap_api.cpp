@@ -29,7 +29,7 @@ int band_variants(int nx, int nt, bool mixed, int* out, int cap);
 int slab_waves(int cls);
 int band_waves(int cls);
 int band_sides(int cls);
-int band_group_class(int cls, int min_nb, int count, int ncu, bool mixed);
+int band_group_class(int cls, int min_nb, int count, int ncu);
 bool spec_supported(int nx, int ny, int nt);
 size_t spec_workspace_bytes(int nx, int nt);
 int spec_launch(const KernelArgs& a, hipStream_t st);
@@ -436,7 +436,7 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
       const snap_sample_desc& d = p->descs[id];
       min_nb = std::min<int>(min_nb, (int)(((int64_t)d.nx * (d.nt - 1) + 15) / 16));
     }
-    g.cls = band_group_class(g.cls, min_nb, (int)g.ids.size(), ncu, mixed);
+    g.cls = band_group_class(g.cls, min_nb, (int)g.ids.size(), ncu);
   }
   // longest samples first inside a group; most expensive groups first
   for (auto& g : p->groups)

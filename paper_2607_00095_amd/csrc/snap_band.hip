@@ -1142,6 +1142,48 @@ __device__ __attribute__((always_inline)) void split_backward(const Ctx& C, cons
   backward_sweep<BB, NW, R>(C, WL, sh, Y, xout, BackRange{Kb - 1, 0, Kb + BB, true, true, true, addlam});
 }
 
+// Solve S x = rin (internal order) with a two-sided factor in one
+// workgroup: forward substitution of both sides and the separator, then the
+// backward substitution of both sides (x canonical, every row written).
+template <int BB, int NW, typename R>
+__device__ __attribute__((always_inline)) void split_sweeps(const Ctx& C, const WsLayout& WL,
+                                                            BandShared<BB, NW, R>& sh, double* x) {
+  const double* rin = (const double*)(C.ws + WL.rin);
+  double* Y = (double*)(C.ws + WL.Y);
+  forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kTop));
+  forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kBottom));
+  forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kSep));
+  split_backward<BB, NW, R>(C, WL, sh, 0, x, nullptr);
+  split_backward<BB, NW, R>(C, WL, sh, 1, x, nullptr);
+}
+
+// Float64 iterative refinement of x (canonical) against rvec with a two-sided
+// factor, in one workgroup: at most max_ref rounds, until the Schur residual
+// (matrix free, float64) is below max(1e-13 ||rvec||, abs_floor).  Returns
+// the rounds taken.  Uses res, rin and t as scratch.
+template <int BB, int NW, typename R>
+__device__ int split_refine(const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, double* x, int max_ref,
+                            double abs_floor) {
+  const double* rvec = (const double*)(C.ws + WL.rvec);
+  double* res = (double*)(C.ws + WL.res);
+  double* rin = (double*)(C.ws + WL.rin);
+  double* dx = (double*)(C.ws + WL.t);
+  double rn = 0.0;
+  for (int r = threadIdx.x; r < C.m; r += NW * kWave) rn = fmax(rn, fabs(rvec[r]));
+  rn = block_max<NW>(rn, sh.red, 1);
+  int refines = 0;
+  for (int it = 0; it < max_ref; ++it) {
+    const double rm = schur_residual<NW>(C, WL, x, res, sh.red);
+    if (!(rm > fmax(1e-13 * rn, abs_floor))) break;
+    to_internal<NW>(C, res, rin);
+    split_sweeps<BB, NW, R>(C, WL, sh, dx);
+    for (int r = threadIdx.x; r < C.m; r += NW * kWave) x[r] += dx[r];
+    __syncthreads();
+    ++refines;
+  }
+  return refines;
+}
+
 // h of row (k, x) at u + alpha p
 __device__ __forceinline__ double h_trial(const Ctx& C, const double* pv, double alpha, int k, int x) {
   const size_t b0 = (size_t)k * C.nx;
@@ -1289,12 +1331,8 @@ SNAP_BAND_KERNEL void band_soc(KernelArgs A) {
   }
   __syncthreads();
   if constexpr (SPLIT) {
-    double* Y = (double*)(C.ws + WL.Y);
-    forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kTop));
-    forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kBottom));
-    forward_sweep<BB, NW, R>(C, WL, sh, rin, Y, make_part<BB>(C, kSep));
-    split_backward<BB, NW, R>(C, WL, sh, 0, z, nullptr);
-    split_backward<BB, NW, R>(C, WL, sh, 1, z, nullptr);
+    split_sweeps<BB, NW, R>(C, WL, sh, z);
+    if (sizeof(R) == 4) (void)split_refine<BB, NW, R>(C, WL, sh, z, 6, 0.1 * A.opt.tol_h);
   } else {
     (void)solve_with_factor<BB, NW, R>(C, WL, sh, false, z, 6, 0.1 * A.opt.tol_h, false);
   }
@@ -1433,7 +1471,9 @@ SNAP_BAND_KERNEL void band_adjoint(KernelArgs A) {
 // Kernels of the two-sided factorization (see the parts section): launches
 // marked "two per sample" run the top part in workgroup 2i and the bottom
 // part in workgroup 2i + 1 of sample order[i]; the separator kernels run one
-// workgroup per sample.  Float64 only (the plain solve needs no refinement).
+// workgroup per sample.  With a float32 factor the float64 refinement rounds
+// (the local phase of the Newton solve, the adjoint) run in one workgroup per
+// sample over all three parts of the factor.
 
 // rows of a side: the top assembles block rows [0, K + BB), the bottom
 // [K + BB, NB) and its own copy of the separator rows (no right-hand side)
@@ -1508,7 +1548,30 @@ SNAP_BAND_KERNEL void band_split_solve(KernelArgs A) {
   const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
   const BandState* S = (const BandState*)(C.ws + WL.hdr);
   if (S->phase != 0) return;
-  split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.lamp), C.lam);
+  // float64: lam+ = lam + dlam directly; float32 factor: dlam to z, refined
+  // and added by band_split_refine
+  if (sizeof(R) == 8)
+    split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.lamp), C.lam);
+  else
+    split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.z), nullptr);
+}
+
+// (one per sample, float32 factor) float64 refinement of dlam in the local
+// phase (as the one-sided mixed solve), then lam+ = lam + dlam
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_refine(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0) return;
+  double* z = (double*)(C.ws + WL.z);
+  double* lamp = (double*)(C.ws + WL.lamp);
+  const int refines = S->hinf <= 1e-6 ? split_refine<BB, NW, R>(C, WL, sh, z, 6, 0.1 * A.opt.tol_h) : 0;
+  for (int r = threadIdx.x; r < C.m; r += NW * kWave) lamp[r] = C.lam[r] + z[r];
+  if (threadIdx.x == 0) S->refines += refines;
 }
 
 // adjoint, (two per sample): a side's right-hand side and forward
@@ -1580,7 +1643,14 @@ SNAP_BAND_KERNEL void band_split_adj4(KernelArgs A) {
   const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
   const BandState* S = (const BandState*)(C.ws + WL.hdr);
   const bool have = (A.opt.flags & SNAP_FLAG_KEEP_FACTOR) != 0 && S->factor_ok == 1;
-  adjoint_finish<NW>(A, C, D, sid, (const double*)(C.ws + WL.lamp), have ? 0 : S->adj_bad, 0);
+  double* b = (double*)(C.ws + WL.lamp);
+  int refines = 0;
+  if constexpr (sizeof(R) == 4) {
+    // float32 factor: refine b to working precision, as the one-sided adjoint
+    __shared__ BandShared<BB, NW, R> sh;
+    refines = split_refine<BB, NW, R>(C, WL, sh, b, 6, 0.0);
+  }
+  adjoint_finish<NW>(A, C, D, sid, b, have ? 0 : S->adj_bad, refines);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -1626,9 +1696,8 @@ static void launch_band(const KernelArgs& a, hipStream_t st) {
 // the two-sided form: the same Newton loop with each factorization and
 // backward substitution split over two workgroups per sample (see the parts
 // section) and the separator's factorization in a launch of its own
-template <int BB, int NW>
+template <int BB, int NW, typename R>
 static void launch_band_split(const KernelArgs& a, hipStream_t st) {
-  using R = double;
   const dim3 one(a.count), two(2 * a.count), block(NW * kWave);
   if (a.backward) {
     hipLaunchKernelGGL((band_split_adj1<BB, NW, R>), two, block, 0, st, a);
@@ -1647,6 +1716,7 @@ static void launch_band_split(const KernelArgs& a, hipStream_t st) {
     if (tm) timer_mark(tm, kTimedBandFactor, st);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_split_solve<BB, NW, R>), two, block, 0, st, a);
+    if (sizeof(R) == 4) hipLaunchKernelGGL((band_split_refine<BB, NW, R>), one, block, 0, st, a);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_step<BB, NW, R>), one, block, 0, st, a);
     if (a.opt.flags & SNAP_FLAG_SOC) hipLaunchKernelGGL((band_soc<BB, NW, R, true>), one, block, 0, st, a);
@@ -1661,18 +1731,17 @@ static void launch_band_split(const KernelArgs& a, hipStream_t st) {
 
 // class = BB + kBandAlt * alt: alt 0 is the default launch shape (four
 // wavefronts for BB <= 9, eight above), alt 1 the alternative (eight, BB <= 9),
-// alt 2 the two-sided form (BB >= 13, float64)
+// alt 2 the two-sided form (BB >= 13)
 constexpr int kBandAlt = 32;
 constexpr int kBandSplit = 2 * kBandAlt;
 
 // The two-sided form halves a factorization's chain of panel steps at the
 // cost of a third launch (the separator, BB panel steps) and twice the
 // workgroups; it is the default where the chain is long (wide bands, at least
-// 40 BB block rows) and the factors are float64 (the mixed form's refinement
-// sweeps are one-sided).
-static bool split_pays(int nx, int nt, int bb, bool mixed) {
+// 40 BB block rows).
+static bool split_pays(int nx, int nt, int bb) {
   const int64_t m = (int64_t)nx * (nt - 1), nb = (m + kT - 1) / kT;
-  return !mixed && bb >= 13 && nb >= 40 * bb;
+  return bb >= 13 && nb >= 40 * bb;
 }
 
 template <typename R>
@@ -1707,10 +1776,10 @@ static int launch_bb(int cls, const KernelArgs& a, hipStream_t st) {
       case 9: launch_band<9, 8, R>(a, st); break;
       default: return SNAP_EUNSUPPORTED;
     }
-  } else if (alt == 2 && std::is_same<R, double>::value) {
+  } else if (alt == 2) {
     switch (bb) {
-      case 13: launch_band_split<13, 8>(a, st); break;
-      case 17: launch_band_split<17, 8>(a, st); break;
+      case 13: launch_band_split<13, 8, R>(a, st); break;
+      case 17: launch_band_split<17, 8, R>(a, st); break;
       default: return SNAP_EUNSUPPORTED;
     }
   } else {
@@ -1730,7 +1799,7 @@ bool band_supported(int nx, int nt, bool mixed) {
 int band_class(int nx, int nt, bool mixed) {
   if (!band_supported(nx, nt, mixed)) return -1;
   const int bb = pick_bb(band_bb(nx, nt));
-  return split_pays(nx, nt, bb, mixed) ? bb + kBandSplit : bb;
+  return split_pays(nx, nt, bb) ? bb + kBandSplit : bb;
 }
 
 // Classes the autotuner may choose between for a shape (default first): the
@@ -1748,7 +1817,7 @@ int band_variants(int nx, int nt, bool mixed, int* out, int cap) {
     out[n++] = bb + kBandAlt;
   } else if (cls != bb) {
     out[n++] = bb;
-  } else if (!mixed && nb >= 3 * bb) {
+  } else if (nb >= 3 * bb) {
     out[n++] = bb + kBandSplit;
   }
   return n;
@@ -1763,13 +1832,13 @@ int band_sides(int cls) { return cls / kBandAlt == 2 ? 2 : 1; }
 // The default class of a whole group: a group that leaves CUs idle (at most
 // one sample per CU) takes the shape that puts more of a CU on each sample,
 // eight wavefronts at BB <= 9, the two-sided factorization at BB >= 13
-// (float64; every sample's parts at least BB block rows).  min_nb is the
-// fewest block rows of the group's samples.
-int band_group_class(int cls, int min_nb, int count, int ncu, bool mixed) {
+// (every sample's parts at least BB block rows).  min_nb is the fewest block
+// rows of the group's samples.
+int band_group_class(int cls, int min_nb, int count, int ncu) {
   const int bb = cls % kBandAlt;
   if (cls / kBandAlt != 0 || count > ncu) return cls;
   if (bb <= 9) return bb + kBandAlt;
-  if (!mixed && min_nb >= 3 * bb) return bb + kBandSplit;
+  if (min_nb >= 3 * bb) return bb + kBandSplit;
   return cls;
 }
 

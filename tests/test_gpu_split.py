@@ -112,8 +112,26 @@ def test_two_sided_agrees_with_one_sided(nx, nt):
     assert rel_err(g2, g1) <= 1e-11
 
 
-def test_mixed_precision_keeps_the_one_sided_form():
+@pytest.mark.parametrize("nx,nt", [(192, 5), (256, 9)])
+def test_two_sided_mixed_precision(nx, nt):
+    # float32 factor: the Newton solve refines in the local phase and the
+    # adjoint to working precision, with one workgroup sweeping all three
+    # parts of the two-sided factor
+    b = synthgen.burgers_batch(batch=2, nx=nx, nt=nt, dt=_dt(nx), seed=5 * nx + nt)
+    opts = snap.Options(precision=snap.PREC_MIXED, flags=snap.FLAG_KEEP_FACTOR)
+    res = gpu_project(b, plan=_forced(b, opts))
+    check_samples(b, res, [0, 1], 1e-6, 1e-4)
+    _check_adjoint(b, res, synthgen.upstream_grad(b, seed=11), 1e-6)
+    # the adjoint refines to working precision: refinement rounds ran
+    _, st = gpu_backward(res, synthgen.upstream_grad(b, seed=11))
+    assert st["refine_steps"].sum() > 0
+    # without a kept factor the adjoint factors again in float32
+    res2 = gpu_project(b, plan=_forced(b, snap.Options(precision=snap.PREC_MIXED)))
+    _check_adjoint(b, res2, synthgen.upstream_grad(b, seed=11), 1e-6)
+
+
+def test_mixed_two_sided_default_on_long_wide_bands():
     b = synthgen.burgers_batch(batch=1, nx=256, nt=45, dt=_dt(256), seed=2)
-    plan = snap.Plan.from_batch(b, snap.Options(precision=snap.PREC_MIXED))
-    assert "two-sided" not in plan.describe()
-    assert all(c < SPLIT for c in plan.group_classes(0))
+    res = gpu_project(b, snap.Options(precision=snap.PREC_MIXED))
+    assert "two-sided" in res["plan"].describe()
+    check_samples(b, res, [0], 1e-6, 1e-4)
