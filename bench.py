@@ -381,6 +381,25 @@ def main():
                           "plan_create_s": tune_s,
                           "launch_groups": planb.describe().strip().splitlines()}
 
+        # the constrained flow-matching sampler around the projection: N
+        # substeps of shoot -> project (plain FP64, one plan and workspace for
+        # all) -> pull back, from a N(0, 1) prior draw towards a Gaussian of
+        # spread 0.05 about the batch's u_hat
+        nsub, calls = 4, 2
+        planp = snap.Plan.from_batch(batch)
+        u0 = torch.from_numpy(synthgen.prior_sample(batch, seed=11)).to(dev)
+        snap.pcfm_sample(planp, u0, uhat, 0.05, nsub, aux, stream)
+        torch.cuda.synchronize()
+        ep0, ep1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ep0.record(stream)
+        for _ in range(calls):
+            _, _, okp = snap.pcfm_sample(planp, u0, uhat, 0.05, nsub, aux, stream)
+        ep1.record(stream)
+        torch.cuda.synchronize()
+        msp = ep0.elapsed_time(ep1) / calls
+        out["pcfm"] = {"substeps": nsub, "ms_per_call": msp, "ms_per_substep": msp / nsub,
+                       "converged_every_substep": int(okp[:B].sum().item())}
+
     if banded:
         # roofline of the dominant kernel, the banded factorization: the
         # method's flops (m b^2 per factorization, one per Newton step of
