@@ -28,6 +28,12 @@
 // The factor (L_JJ^{-1}, L(I,J), D) is written to the workspace for the
 // backward substitution and for the adjoint.
 //
+// Long wide bands are factored in a two-sided form: two workgroups per sample
+// factor the band from both ends toward a separator of BB block rows, which a
+// third sweep factors last (the parts section below).  With the option flag
+// SNAP_FLAG_SOC a rejected full step gets one second-order correction
+// (band_soc) before halving.
+//
 // Precision R: double (plain form) or float (mixed form: float32 factor and
 // solves, float64 residual r - S x from the stencil, iterative refinement).
 #include <type_traits>
