@@ -309,11 +309,11 @@ __device__ void assemble_all(const Ctx& C, const WsLayout& WL) {
 // Right-hand side h - J W^{-1} g alone (rvec canonical, rin internal order),
 // for a Newton step solved with the factor of an earlier iteration.
 template <int NW>
-__device__ void assemble_rhs(const Ctx& C, const WsLayout& WL) {
+__device__ void assemble_rhs_rows(const Ctx& C, const WsLayout& WL, int r0, int r1) {
   double* rvec = (double*)(C.ws + WL.rvec);
   double* rin = (double*)(C.ws + WL.rin);
   const int nx = C.nx;
-  for (int r = threadIdx.x; r < C.M; r += NW * kWave) {
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += NW * kWave) {
     if (r >= C.m) { rin[r] = 0.0; continue; }
     const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
     double rhs = h_row(C, k, x);
@@ -329,6 +329,11 @@ __device__ void assemble_rhs(const Ctx& C, const WsLayout& WL) {
     rin[r] = rhs;
   }
   __syncthreads();
+}
+
+template <int NW>
+__device__ void assemble_rhs(const Ctx& C, const WsLayout& WL) {
+  assemble_rhs_rows<NW>(C, WL, 0, C.M);
 }
 
 // scatter the prefetched contributions of row a of block row I into the staging tile
@@ -1507,13 +1512,41 @@ SNAP_BAND_KERNEL void band_split_factor(KernelArgs A) {
   const Ctx C = make_ctx(A, D, sid, false);
   const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
   BandState* S = (BandState*)(C.ws + WL.hdr);
-  if (S->phase == 2) return;
+  // (a reused factor: band_split_rhs did this step's work; the final factor
+  // at the returned point, phase 1, is always taken)
+  if (S->phase == 2 || (S->phase == 0 && S->reuse)) return;
   const Part PT = make_part<BB>(C, side ? kBottom : kTop);
   assemble_part<NW>(C, WL, PT);
   if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
   __syncthreads();
   const int bad = factor_sweep<BB, NW, R>(C, WL, sh, PT);
   if (threadIdx.x == 0) S->side_bad[side] = bad;
+}
+
+// (two per sample) Local phase (||h||_inf <= kReuseH): the step is solved
+// with the previous iteration's factor and float64 refinement, as on
+// one-sided wide bands.  Decides that (the top workgroup sets the flag; no
+// other workgroup of this launch reads it), and then forms the side's
+// right-hand side and its forward substitution in place of the
+// factorization.
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_rhs(KernelArgs A) {
+  const int side = blockIdx.x & 1;
+  const int sid = A.order[blockIdx.x >> 1];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  const int phase = S->phase;
+  if (phase == 2) return;
+  const bool reuse = phase == 0 && S->factored && S->hinf <= kReuseH;
+  if (threadIdx.x == 0 && side == 0) S->reuse = reuse ? 1 : 0;
+  if (!reuse) return;
+  const Part PT = make_part<BB>(C, side ? kBottom : kTop);
+  const int s1 = (C.NB - PT.Kb) * kT;
+  assemble_rhs_rows<NW>(C, WL, side ? s1 : 0, side ? C.M : s1);
+  forward_sweep<BB, NW, R>(C, WL, sh, (const double*)(C.ws + WL.rin), (double*)(C.ws + WL.Y), PT);
 }
 
 // (one per sample) factor the separator; the state update of band_factor
@@ -1527,6 +1560,12 @@ SNAP_BAND_KERNEL void band_split_sep(KernelArgs A) {
   BandState* S = (BandState*)(C.ws + WL.hdr);
   const int phase = S->phase;
   if (phase == 2) return;
+  if (phase == 0 && S->reuse) {
+    // the separator's forward substitution with the stored factor
+    forward_sweep<BB, NW, R>(C, WL, sh, (const double*)(C.ws + WL.rin), (double*)(C.ws + WL.Y),
+                             make_part<BB>(C, kSep));
+    return;
+  }
   if (threadIdx.x < 4) sh.flag[threadIdx.x] = 0;
   __syncthreads();
   const int bad = factor_sweep<BB, NW, R>(C, WL, sh, make_part<BB>(C, kSep)) | S->side_bad[0] | S->side_bad[1];
@@ -1554,16 +1593,17 @@ SNAP_BAND_KERNEL void band_split_solve(KernelArgs A) {
   const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
   const BandState* S = (const BandState*)(C.ws + WL.hdr);
   if (S->phase != 0) return;
-  // float64: lam+ = lam + dlam directly; float32 factor: dlam to z, refined
-  // and added by band_split_refine
-  if (sizeof(R) == 8)
+  // float64 with a fresh factor: lam+ = lam + dlam directly; a float32 or
+  // reused factor: dlam to z, refined and added by band_split_refine
+  if (sizeof(R) == 8 && !S->reuse)
     split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.lamp), C.lam);
   else
     split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.z), nullptr);
 }
 
-// (one per sample, float32 factor) float64 refinement of dlam in the local
-// phase (as the one-sided mixed solve), then lam+ = lam + dlam
+// (one per sample) float64 refinement of dlam, then lam+ = lam + dlam: with
+// a float32 factor in the local phase (as the one-sided mixed solve), and
+// with a reused factor; nothing with a fresh float64 factor
 template <int BB, int NW, typename R>
 SNAP_BAND_KERNEL void band_split_refine(KernelArgs A) {
   const int sid = A.order[blockIdx.x];
@@ -1573,9 +1613,12 @@ SNAP_BAND_KERNEL void band_split_refine(KernelArgs A) {
   const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
   BandState* S = (BandState*)(C.ws + WL.hdr);
   if (S->phase != 0) return;
+  const bool reuse = S->reuse != 0;
+  if (sizeof(R) == 8 && !reuse) return;
   double* z = (double*)(C.ws + WL.z);
   double* lamp = (double*)(C.ws + WL.lamp);
-  const int refines = S->hinf <= 1e-6 ? split_refine<BB, NW, R>(C, WL, sh, z, 6, 0.1 * A.opt.tol_h) : 0;
+  const int refines =
+      (S->hinf <= 1e-6 || reuse) ? split_refine<BB, NW, R>(C, WL, sh, z, 6, 0.1 * A.opt.tol_h) : 0;
   for (int r = threadIdx.x; r < C.m; r += NW * kWave) lamp[r] = C.lam[r] + z[r];
   if (threadIdx.x == 0) S->refines += refines;
 }
@@ -1717,12 +1760,13 @@ static void launch_band_split(const KernelArgs& a, hipStream_t st) {
   KernelTimer* tm = tl_timer;
   for (int it = 0; it < a.opt.max_newton; ++it) {
     if (tm) timer_mark(tm, kTimedBandFactor, st);
+    hipLaunchKernelGGL((band_split_rhs<BB, NW, R>), two, block, 0, st, a);
     hipLaunchKernelGGL((band_split_factor<BB, NW, R>), two, block, 0, st, a);
     hipLaunchKernelGGL((band_split_sep<BB, NW, R>), one, block, 0, st, a);
     if (tm) timer_mark(tm, kTimedBandFactor, st);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_split_solve<BB, NW, R>), two, block, 0, st, a);
-    if (sizeof(R) == 4) hipLaunchKernelGGL((band_split_refine<BB, NW, R>), one, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_refine<BB, NW, R>), one, block, 0, st, a);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_step<BB, NW, R>), one, block, 0, st, a);
     if (a.opt.flags & SNAP_FLAG_SOC) hipLaunchKernelGGL((band_soc<BB, NW, R, true>), one, block, 0, st, a);
