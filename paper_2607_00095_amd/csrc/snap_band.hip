@@ -964,6 +964,7 @@ struct BandState {
   int reuse;        // this iteration's step is solved with that factor
   int side_bad[2];  // two-sided form: a side's sweep met a non-positive pivot
   int adj_bad;      // two-sided adjoint: its factorization met one
+  int round;        // two-sided form: a parallel refinement round of the step is due
   int soc_try;      // the full step failed and raised ||h||_1: band_soc tries a correction
   double soc_dd, soc_pp;   // (u - u_hat).p and p.p of that step
   double mu, uscale, h1, hinf, stinf;
@@ -1601,6 +1602,86 @@ SNAP_BAND_KERNEL void band_split_solve(KernelArgs A) {
     split_backward<BB, NW, R>(C, WL, sh, side, (double*)(C.ws + WL.z), nullptr);
 }
 
+// A refinement round of the two-sided step, spread over the solve's
+// launches: band_split_res (one per sample) decides it and forms the
+// internal-order residual; band_split_rfwd (two per sample) and
+// band_split_rsep (one) run the forward substitution; band_split_rbwd (two)
+// the backward substitution, adding the correction to dlam (z).  Rounds
+// still due after it are swept by band_split_refine in one workgroup.
+template <int BB, int NW, typename R>
+__device__ __forceinline__ bool split_refining(const BandState* S) {
+  return S->phase == 0 && ((sizeof(R) == 4 && S->hinf <= 1e-6) || S->reuse);
+}
+
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_res(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ double red[NW][4];
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  BandState* S = (BandState*)(C.ws + WL.hdr);
+  if (S->phase == 2) return;
+  int round = 0;
+  if (split_refining<BB, NW, R>(S)) {
+    const double* rvec = (const double*)(C.ws + WL.rvec);
+    double* res = (double*)(C.ws + WL.res);
+    double rn = 0.0;
+    for (int r = threadIdx.x; r < C.m; r += NW * kWave) rn = fmax(rn, fabs(rvec[r]));
+    rn = block_max<NW>(rn, red, 1);
+    const double rm = schur_residual<NW>(C, WL, (const double*)(C.ws + WL.z), res, red);
+    if (rm > fmax(1e-13 * rn, 0.1 * A.opt.tol_h)) {
+      to_internal<NW>(C, res, (double*)(C.ws + WL.rin));
+      round = 1;
+    }
+  }
+  if (threadIdx.x == 0) {
+    S->round = round;
+    if (round) S->refines += 1;
+  }
+}
+
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_rfwd(KernelArgs A) {
+  const int side = blockIdx.x & 1;
+  const int sid = A.order[blockIdx.x >> 1];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0 || !S->round) return;
+  forward_sweep<BB, NW, R>(C, WL, sh, (const double*)(C.ws + WL.rin), (double*)(C.ws + WL.Y),
+                           make_part<BB>(C, side ? kBottom : kTop));
+}
+
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_rsep(KernelArgs A) {
+  const int sid = A.order[blockIdx.x];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0 || !S->round) return;
+  forward_sweep<BB, NW, R>(C, WL, sh, (const double*)(C.ws + WL.rin), (double*)(C.ws + WL.Y),
+                           make_part<BB>(C, kSep));
+}
+
+template <int BB, int NW, typename R>
+SNAP_BAND_KERNEL void band_split_rbwd(KernelArgs A) {
+  const int side = blockIdx.x & 1;
+  const int sid = A.order[blockIdx.x >> 1];
+  const snap_sample_desc D = A.descs[sid];
+  __shared__ BandShared<BB, NW, R> sh;
+  const Ctx C = make_ctx(A, D, sid, false);
+  const WsLayout WL = ws_layout(C.nx, C.nt, BB, sizeof(R));
+  const BandState* S = (const BandState*)(C.ws + WL.hdr);
+  if (S->phase != 0 || !S->round) return;
+  double* z = (double*)(C.ws + WL.z);
+  split_backward<BB, NW, R>(C, WL, sh, side, z, z);     // z += correction
+}
+
 // (one per sample) float64 refinement of dlam, then lam+ = lam + dlam: with
 // a float32 factor in the local phase (as the one-sided mixed solve), and
 // with a reused factor; nothing with a fresh float64 factor
@@ -1766,6 +1847,10 @@ static void launch_band_split(const KernelArgs& a, hipStream_t st) {
     if (tm) timer_mark(tm, kTimedBandFactor, st);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_split_solve<BB, NW, R>), two, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_res<BB, NW, R>), one, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_rfwd<BB, NW, R>), two, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_rsep<BB, NW, R>), one, block, 0, st, a);
+    hipLaunchKernelGGL((band_split_rbwd<BB, NW, R>), two, block, 0, st, a);
     hipLaunchKernelGGL((band_split_refine<BB, NW, R>), one, block, 0, st, a);
     if (tm) timer_mark(tm, kTimedBandSolve, st);
     hipLaunchKernelGGL((band_step<BB, NW, R>), one, block, 0, st, a);
