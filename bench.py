@@ -49,11 +49,11 @@ KERNEL_SOURCES = {
     "diff2d_energy": "paper_2607_00095_amd/csrc/snap_spec.hip",
 }
 # the dominant kernel of each workload; a band factorization launch is one
-# band_factor, or (two-sided form, wide bands) a band_split_factor +
-# band_split_sep pair timed as one
+# band_factor, or (two-sided form, wide bands) a band_split_rhs +
+# band_split_factor + band_split_sep sequence timed as one
 KERNEL_NAMES = {
     "fisher_kpp": "slab_kernel", "mass_ic": "slab_kernel",
-    "burgers_lf": "band_factor", "ragged": "band_factor | band_split_factor+band_split_sep",
+    "burgers_lf": "band_factor", "ragged": "band_factor | band_split_rhs+band_split_factor+band_split_sep",
     "diff2d_energy": "spec_kernel",
 }
 FP64_PEAK_TFLOPS = 78.6
