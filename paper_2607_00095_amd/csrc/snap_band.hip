@@ -776,11 +776,13 @@ __device__ __attribute__((always_inline)) void forward_sweep(
       sh.ring[((J + d) % (BB + 1)) * kT + a] -= s;
     }
     lds_barrier();
+    // (row J's slot takes the entering row; the next step reads it only
+    // after its first barrier, so no barrier is needed here)
     if (t < kT) sh.ring[(J % (BB + 1)) * kT + t] = part_rhs(C, rin, PT, J + BB + 1, t);
 #pragma unroll
     for (int c = 0; c < kT; ++c) cur[c] = nxt[c];
-    lds_barrier();
   }
+  lds_barrier();
   if (PT.kind == kTop || PT.kind == kBottom) {
     double* sr = (double*)(C.ws + WL.sepr) + (PT.kind == kBottom ? BB * kT : 0);
     for (int i = t; i < BB * kT; i += NW * kWave) sr[i] = sh.ring[((PT.steps + i / kT) % (BB + 1)) * kT + (i % kT)];
@@ -846,15 +848,14 @@ __device__ __attribute__((always_inline)) void backward_sweep(
     if (t < 256) sh.Xw[(t >> 4) * kLd + (t & 15)] = (double)dcur;
     lds_barrier();
     if (t < kT) {
+      // lanes 0..15 of wavefront 0: entry t of y_J minus the sum, then
+      // x = L_JJ^{-T} of it with entry c2 read from lane c2 (no barrier)
       double acc = 0.0;
       for (int q = 0; q < NG; ++q) acc += sh.part[q * kT + t];
-      sh.yJ[t] = ycur - acc;
-    }
-    lds_barrier();
-    if (t < kT) {
+      const double yv = ycur - acc;
       double x = 0.0;
 #pragma unroll
-      for (int c2 = 0; c2 < kT; ++c2) x += sh.Xw[c2 * kLd + t] * sh.yJ[c2];   // L_JJ^{-T}
+      for (int c2 = 0; c2 < kT; ++c2) x += sh.Xw[c2 * kLd + t] * lane_bcast(yv, c2);   // L_JJ^{-T}
       sh.ring[(J % (BB + 1)) * kT + t] = x;
       const int r = BR.rev ? C.M - 1 - (J * kT + t) : J * kT + t;
       if (BR.write_x && r < C.m) {
