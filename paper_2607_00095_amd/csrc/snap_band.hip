@@ -119,6 +119,10 @@ struct WsLayout {
   size_t total;
 };
 
+// panels in flight in the forward and backward substitution sweeps (the
+// widest bands keep one stage fewer in the backward sweep's registers)
+constexpr int kFwdDepth = 3;
+constexpr int back_depth(int BB) { return BB >= 13 ? 3 : 4; }
 constexpr int kContrib = 16;   // stencil contributions to one row of S (4 variables x 4 rows)
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -438,10 +442,15 @@ __device__ __forceinline__ void part_row(const Ctx& C, const WsLayout& WL, const
 }
 
 // right-hand side of row a of block row I (sweep coordinates)
+__device__ __forceinline__ long part_rhs_index(const Ctx& C, const Part& P, int I, int a) {
+  if (I >= P.rows) return -1;
+  if (P.kind == kBottom) return I < P.Kb ? C.M - 1 - (I * kT + a) : -1;
+  return (long)I * kT + a;
+}
+
 __device__ __forceinline__ double part_rhs(const Ctx& C, const double* rin, const Part& P, int I, int a) {
-  if (I >= P.rows) return 0.0;
-  if (P.kind == kBottom) return I < P.Kb ? rin[C.M - 1 - (I * kT + a)] : 0.0;
-  return rin[(size_t)I * kT + a];
+  const long i = part_rhs_index(C, P, I, a);
+  return i < 0 ? 0.0 : rin[i];
 }
 
 // Entry [a][b] of separator block (i, i - d) (local block rows): the top's
@@ -734,53 +743,82 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
 // exports its update of the separator's right-hand side, the separator's
 // sweep starts from both).  Threads t < 16*BB own row (t % 16) of block
 // L(J+1+t/16, J); threads 16*BB..16*BB+15 own a row of L_JJ^{-1}; each keeps
-// its 16 values of the next panel in flight.
+// its 16 values.  Both sweeps keep the loads of the next few panels (kFwdDepth,
+// back_depth) in flight: a stage is refilled right after its step, every load is in
+// bounds and unconditional (values a step does not need are masked where they
+// are used), so each step waits only for the stage it consumes and the HBM
+// latency overlaps the dependent chain of the steps in between.
 template <int BB, int NW, typename R>
 __device__ __attribute__((always_inline)) void forward_sweep(
     const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* rin, double* Y, const Part& PT) {
   static_assert(NW * kWave >= kT * (BB + 1), "forward sweep needs 16*(BB+1) threads");
   const R* Lg = (const R*)(C.ws + WL.L);
-  const int t = threadIdx.x;
+  // (fresh: the thread-derived offsets below are formed inside each sweep,
+  // not hoisted into registers held across a caller's refinement loop)
+  const int t = fresh_v(threadIdx.x);
   const bool offd = t < kT * BB, diag = t >= kT * BB && t < kT * (BB + 1);
-  const int d = offd ? 1 + t / kT : 0, a = offd ? t % kT : t - kT * BB;
+  // threads past 16*(BB+1) load (and never use) a row of block 0
+  const int d = offd ? 1 + t / kT : 0, a = offd ? t % kT : (t - kT * BB) & (kT - 1);
   const double* sr_in = (const double*)(C.ws + WL.sepr);
   for (int i = t; i < (BB + 1) * kT; i += NW * kWave) {
     const int I = i / kT, aa = i - I * kT;
     sh.ring[i] = PT.kind == kSep ? (I < BB ? sep_rhs<BB>(sr_in, I, aa) : 0.0) : part_rhs(C, rin, PT, I, aa);
   }
-  R cur[kT], nxt[kT];
-  auto load = [&](int J, R* dst) {
-    if ((offd || diag) && J < PT.steps) {
-      const R* src = Lg + ((size_t)part_slot(C, PT, J) * (BB + 1) + d) * 256 + a * kT;
-#pragma unroll
-      for (int c = 0; c < kT; ++c) dst[c] = src[c];
-    }
+  // one pipeline stage: this thread's row of its block of panel J and the
+  // right-hand side entry of the block row that enters after step J
+  struct Stage {
+    R l[kT];
+    double r;
   };
-  load(0, cur);
-  lds_barrier();
-  for (int J = 0; J < PT.steps; ++J) {
-    load(J + 1, nxt);
+  Stage st[kFwdDepth];
+  const int last = PT.steps - 1;
+  auto load = [&](int J, Stage& s) {
+    const int Jc = J < last ? J : last;        // stages past the last panel are never used
+    const R* src = Lg + ((size_t)part_slot(C, PT, Jc) * (BB + 1) + d) * 256 + a * kT;
+#pragma unroll
+    for (int c = 0; c < kT; ++c) s.l[c] = src[c];
+    const long ri = part_rhs_index(C, PT, Jc + BB + 1, t & (kT - 1));
+    s.r = rin[ri < 0 ? 0 : ri];
+  };
+  auto step = [&](int J, const Stage& s) {
     if (diag) {
       const double* rJ = &sh.ring[(J % (BB + 1)) * kT];
       double y = 0.0;
 #pragma unroll
-      for (int c = 0; c < kT; ++c) y += (double)cur[c] * rJ[c];
+      for (int c = 0; c < kT; ++c) y += (double)s.l[c] * rJ[c];
       sh.yJ[a] = y;
       Y[(size_t)part_slot(C, PT, J) * kT + a] = y;
     }
     lds_barrier();
     if (offd && J + d < PT.rows) {
-      double s = 0.0;
+      double sum = 0.0;
 #pragma unroll
-      for (int c = 0; c < kT; ++c) s += (double)cur[c] * sh.yJ[c];
-      sh.ring[((J + d) % (BB + 1)) * kT + a] -= s;
+      for (int c = 0; c < kT; ++c) sum += (double)s.l[c] * sh.yJ[c];
+      sh.ring[((J + d) % (BB + 1)) * kT + a] -= sum;
     }
     lds_barrier();
     // (row J's slot takes the entering row; the next step reads it only
     // after its first barrier, so no barrier is needed here)
-    if (t < kT) sh.ring[(J % (BB + 1)) * kT + t] = part_rhs(C, rin, PT, J + BB + 1, t);
+    if (t < kT) sh.ring[(J % (BB + 1)) * kT + t] = part_rhs_index(C, PT, J + BB + 1, t) >= 0 ? s.r : 0.0;
+  };
+  if (PT.steps > 0) {
+    // stages filled in the order the loop refills them, so the wait before
+    // each step covers that stage's loads only
 #pragma unroll
-    for (int c = 0; c < kT; ++c) cur[c] = nxt[c];
+    for (int b = 0; b < kFwdDepth; ++b) {
+      load(b, st[b]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    lds_barrier();
+    for (int J0 = 0; J0 < PT.steps; J0 += kFwdDepth) {
+#pragma unroll
+      for (int b = 0; b < kFwdDepth; ++b) {
+        const int J = J0 + b;
+        if (J >= PT.steps) break;
+        step(J, st[b]);
+        load(J + kFwdDepth, st[b]);
+      }
+    }
   }
   lds_barrier();
   if (PT.kind == kTop || PT.kind == kBottom) {
@@ -793,11 +831,11 @@ __device__ __attribute__((always_inline)) void forward_sweep(
 // backward substitution x = L^{-T} D^{-1} Y; x is written in canonical row
 // order.  Thread (c = t % 16, g = t / 16) accumulates the (d, a) pairs
 // pq = g, g + NG, ... of sum_{d,a} L(J+d,J)[a][c] x_{J+d}[a] and holds one
-// element of L_JJ^{-1}; the next panel's values are loaded one step ahead.
-// Panels jhi down to jlo; blocks at rows >= nbr are absent.  rev: the bottom
-// part's reversed coordinates (panel J stored as block NB-1-J).  keep_ring:
-// the window already holds x of rows jhi+1 .. jhi+BB.  Rows are written to
-// xout (canonical order, plus addlam when given) only with write_x.
+// element of L_JJ^{-1}.  Panels jhi down to jlo; blocks at rows >= nbr are
+// absent.  rev: the bottom part's reversed coordinates (panel J stored as
+// block NB-1-J).  keep_ring: the window already holds x of rows
+// jhi+1 .. jhi+BB.  Rows are written to xout (canonical order, plus addlam
+// when given) only with write_x.
 struct BackRange {
   int jhi, jlo, nbr;
   bool rev, keep_ring, write_x;
@@ -811,64 +849,102 @@ __device__ __attribute__((always_inline)) void backward_sweep(
   constexpr int NT = NW * kWave;
   constexpr int NG = NT / kT;                       // 16-thread groups
   constexpr int NPQ = (BB * kT + NG - 1) / NG;      // (d, a) pairs per thread
+  constexpr int kBackDepth = back_depth(BB);
   const R* Lg = (const R*)(C.ws + WL.L);
   const double* Dg = (const double*)(C.ws + WL.Dg);
-  const int t = threadIdx.x;
+  // (fresh: the thread-derived offsets below are formed inside each sweep,
+  // not hoisted into registers held across a caller's refinement loop)
+  const int t = fresh_v(threadIdx.x);
   const int cc = t & 15, grp = t >> 4;
   if (!BR.keep_ring)
     for (int i = t; i < (BB + 1) * kT; i += NT) sh.ring[i] = 0.0;
-  R cur[NPQ], nxt[NPQ];
-  R dcur = 0, dnxt = 0;       // element (t / 16, t % 16) of L_JJ^{-1} (t < 256)
-  double ycur = 0.0, ynxt = 0.0;
-  auto load = [&](int J, R* dst, R& dg, double& yv) {
-    if (J < BR.jlo) return;
-    const size_t sl = BR.rev ? C.NB - 1 - J : J;
-    const R* base = Lg + sl * (BB + 1) * 256;
+  // element offsets of the thread's (d, a) pairs inside a panel's blocks; a
+  // spare pair (past BB*16) reads an entry it does not use
+  unsigned off[NPQ];
 #pragma unroll
-    for (int i = 0; i < NPQ; ++i) {
-      const int pq = grp + NG * i;
-      const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
-      dst[i] = (pq < BB * kT && J + d < BR.nbr) ? base[(size_t)d * 256 + a * kT + cc] : (R)0;
-    }
-    if (t < 256) dg = base[t];
-    if (t < kT) yv = Y[sl * kT + t] / Dg[sl * kT + t];
+  for (int i = 0; i < NPQ; ++i) {
+    int pq = grp + NG * i;
+    pq = pq < BB * kT ? pq : BB * kT - 1;
+    const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
+    off[i] = (unsigned)(d * 256 + a * kT + cc);
+  }
+  // one pipeline stage: the thread's L entries of panel J, its element of
+  // L_JJ^{-1}, and for row J*16 + (t % 16): y, D, the canonical index (-1
+  // past the last row) and the multiplier to add, read before the row is
+  // written (addlam may be xout itself)
+  struct Stage {
+    R l[NPQ];
+    R dg;
+    double y, dd, al;
+    int ci;
   };
-  load(BR.jhi, cur, dcur, ycur);
-  lds_barrier();
-  for (int J = BR.jhi; J >= BR.jlo; --J) {
-    load(J - 1, nxt, dnxt, ynxt);
-    double s = 0.0;
+  Stage st[kBackDepth];
+  const double* alsrc = BR.addlam ? BR.addlam : Y;  // any valid address when there is none
+  auto load = [&](int J, Stage& s) {
+    const int Jc = J < BR.jlo ? BR.jlo : J;        // stages past the last panel are never used
+    const unsigned sl = BR.rev ? C.NB - 1 - Jc : Jc;
+    const R* base = Lg + (size_t)sl * (BB + 1) * 256;
+#pragma unroll
+    for (int i = 0; i < NPQ; ++i) s.l[i] = base[off[i]];
+    s.dg = base[t & 255];
+    s.y = Y[sl * kT + cc];
+    s.dd = Dg[sl * kT + cc];
+    const int r = BR.rev ? C.M - 1 - (Jc * kT + cc) : Jc * kT + cc;
+    int ci = -1;
+    if (r < C.m) {
+      const int k = r / C.nx, px = r - k * C.nx;
+      ci = k * C.nx + fold_x(px, C.nx);
+    }
+    s.ci = ci;
+    s.al = alsrc[ci < 0 ? 0 : ci];
+  };
+  auto step = [&](int J, const Stage& s) {
+    const double yd = s.y / s.dd;                 // lanes < 16 use it
+    const int jm = J % (BB + 1);
+    double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < NPQ; ++i) {
       const int pq = grp + NG * i;
       const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
-      if (pq < BB * kT) s += (double)cur[i] * sh.ring[((J + d) % (BB + 1)) * kT + a];
+      const int slot = jm + d > BB ? jm + d - (BB + 1) : jm + d;
+      const double v = (double)s.l[i] * sh.ring[slot * kT + a];
+      sum += (pq < BB * kT && J + d < BR.nbr) ? v : 0.0;
     }
-    sh.part[t] = s;
-    if (t < 256) sh.Xw[(t >> 4) * kLd + (t & 15)] = (double)dcur;
+    sh.part[t] = sum;
+    if (t < 256) sh.Xw[(t >> 4) * kLd + (t & 15)] = (double)s.dg;
     lds_barrier();
     if (t < kT) {
       // lanes 0..15 of wavefront 0: entry t of y_J minus the sum, then
       // x = L_JJ^{-T} of it with entry c2 read from lane c2 (no barrier)
       double acc = 0.0;
       for (int q = 0; q < NG; ++q) acc += sh.part[q * kT + t];
-      const double yv = ycur - acc;
+      const double yv = yd - acc;
       double x = 0.0;
 #pragma unroll
       for (int c2 = 0; c2 < kT; ++c2) x += sh.Xw[c2 * kLd + t] * lane_bcast(yv, c2);   // L_JJ^{-T}
-      sh.ring[(J % (BB + 1)) * kT + t] = x;
-      const int r = BR.rev ? C.M - 1 - (J * kT + t) : J * kT + t;
-      if (BR.write_x && r < C.m) {
-        const int k = r / C.nx, px = r - k * C.nx;
-        const size_t c = (size_t)k * C.nx + fold_x(px, C.nx);
-        xout[c] = BR.addlam ? x + BR.addlam[c] : x;
+      sh.ring[jm * kT + t] = x;
+      if (BR.write_x && s.ci >= 0) xout[s.ci] = BR.addlam ? x + s.al : x;
+    }
+    lds_barrier();
+  };
+  if (BR.jhi >= BR.jlo) {
+    // stages filled in the order the loop refills them, so the wait before
+    // each step covers that stage's loads only
+#pragma unroll
+    for (int b = 0; b < kBackDepth; ++b) {
+      load(BR.jhi - b, st[b]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    lds_barrier();
+    for (int J0 = BR.jhi; J0 >= BR.jlo; J0 -= kBackDepth) {
+#pragma unroll
+      for (int b = 0; b < kBackDepth; ++b) {
+        const int J = J0 - b;
+        if (J < BR.jlo) break;
+        step(J, st[b]);
+        load(J - kBackDepth, st[b]);
       }
     }
-#pragma unroll
-    for (int i = 0; i < NPQ; ++i) cur[i] = nxt[i];
-    dcur = dnxt;
-    ycur = ynxt;
-    lds_barrier();
   }
   __syncthreads();            // x visible to every wavefront
 }

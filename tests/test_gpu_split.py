@@ -135,3 +135,22 @@ def test_mixed_two_sided_default_on_long_wide_bands():
     res = gpu_project(b, snap.Options(precision=snap.PREC_MIXED))
     assert "two-sided" in res["plan"].describe()
     check_samples(b, res, [0], 1e-6, 1e-4)
+
+
+@pytest.mark.parametrize("prec", [snap.PREC_FP64, snap.PREC_MIXED])
+def test_two_sided_refinement_rounds_match_one_sided(prec):
+    # the first refinement round of a two-sided step adds its correction to
+    # the step in place (the backward sweeps read and write the same vector);
+    # a round that lost the step would leave a residual as large as before and
+    # cost extra rounds, so the two forms refine about equally often
+    b = synthgen.burgers_batch(batch=2, nx=256, nt=45, dt=_dt(256), seed=21)
+    opts = snap.Options(precision=prec)
+    two = gpu_project(b, opts)
+    assert "two-sided" in two["plan"].describe()
+    plan_one = snap.Plan.from_batch(b, opts)
+    plan_one.set_group_class(0, 17)
+    one = gpu_project(b, plan=plan_one)
+    assert "two-sided" not in one["plan"].describe()
+    assert (two["stats"]["status"] == 0).all() and (one["stats"]["status"] == 0).all()
+    r2, r1 = two["stats"]["refine_steps"], one["stats"]["refine_steps"]
+    assert (r2 <= r1 + two["stats"]["newton_iters"]).all(), (r2, r1)
