@@ -86,12 +86,11 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 template <int BB, int NW, typename R>
 struct BandShared {
   R P[BB + 1][kTL];        // panel blocks (S, then L after the panel solve)
-  R PD[BB + 1][kTL];       // -L(J+d, J) D_J, the trailing update's right operand
+  R PD[BB + 1][kTL];       // -S(J+d, J), the trailing update's right operand
   R NR[BB + 1][kTL];       // staging area of the entering block row
-  R T[kTL];                // L_JJ^{-T} D_J^{-1}
-  double Xw[kTL];          // L_JJ^{-1} (solves)
+  R T[kTL];                // L_JJ^{-T} D_J^{-1}, then the diagonal block's inverse A_JJ^{-1}
+  R X[kTL];                // L_JJ^{-1}
   double Dv[kT];
-  double rD[kT];           // 1 / D_J
   double ring[(BB + 1) * kT];   // right-hand side / solution window of live block rows
   double newr[kT];
   double yJ[kT];
@@ -119,10 +118,8 @@ struct WsLayout {
   size_t total;
 };
 
-// panels in flight in the forward and backward substitution sweeps (the
-// widest bands keep one stage fewer in the backward sweep's registers)
-constexpr int kFwdDepth = 3;
-constexpr int back_depth(int BB) { return BB >= 13 ? 3 : 4; }
+// panels in flight in the forward and backward substitution sweeps
+constexpr int kFwdDepth = 3, kBackDepth = 3;
 constexpr int kContrib = 16;   // stencil contributions to one row of S (4 variables x 4 rows)
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -599,7 +596,10 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       if (tr[s] == 0) {
         const int d = fresh(sd[s]);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sh.P[d][Mfma<R>::row(lk, e) * kLd + li] = acc[s][e];
+        for (int e = 0; e < 4; ++e) {
+          sh.P[d][Mfma<R>::row(lk, e) * kLd + li] = acc[s][e];
+          if (d > 0) sh.PD[d][Mfma<R>::row(lk, e) * kLd + li] = -acc[s][e];
+        }
       }
     }
     zero_nr();
@@ -607,15 +607,19 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
 
     // (b) wavefront 0: LDL^T of the diagonal block; wavefront 1: next block row
     if (w == 0) {
-      // LDL^T of the symmetric 16x16 diagonal block in registers.  Lanes
-      // 0..15 hold column k = lane of the working matrix (v[i] = A[i][k]) and
-      // entry k of the right-hand side; lanes 16..31 hold column k = lane - 16 of
-      // the identity.  Pivot p broadcasts column p from lane p and every lane
-      // applies the same row operation v[i] -= (A[i][p] / D_p) v[p], so the
-      // matrix lanes eliminate (the right-hand side becomes y = L^{-1} r) while
-      // the identity lanes turn into the columns of X = L^{-1}.  Row p of X is
-      // final after pivot p: T = L^{-T} D^{-1} and the stored X are written as
-      // the sweep goes.  (Lanes 32..63 repeat lanes 0..31.)
+      // LDL^T of the symmetric 16x16 diagonal block A in registers.  Lanes
+      // 0..15 hold column k = lane of the working matrix (v[i] = A[i][k]);
+      // lanes 16..31 hold column k = lane - 16 of the identity.  Pivot p
+      // broadcasts column p from lane p and every lane applies the same row
+      // operation v[i] -= (A[i][p] / D_p) v[p], so the matrix lanes eliminate
+      // while the identity lanes turn into the columns of X = L^{-1}.  Row p
+      // of X is final after pivot p: X and T = L^{-T} D^{-1} go to LDS as the
+      // sweep goes, and the wavefront then forms A^{-1} = T X on MFMA.  The
+      // stored factor holds A^{-1} and M(J+d) = L(J+d, J) L^{-1} = S(J+d, J)
+      // A^{-1}: the substitutions then run on z = L y (the right-hand side
+      // minus the earlier panels' updates, no diagonal solve in the chain),
+      // z(J+d) -= M(J+d) z(J) forward and x(J) = A^{-1} z(J) - sum M^T x
+      // backward.  (Lanes 32..63 repeat lanes 0..31.)
       const int k = fresh_v(lane & (kT - 1));  // (not hoisted: 16 identity values would be)
       const bool xl = (lane & 16) != 0;        // an identity / X lane
       double dmine = 1.0;
@@ -623,7 +627,7 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       double v[kT];
 #pragma unroll
       for (int i = 0; i < kT; ++i) v[i] = xl ? (i == k ? 1.0 : 0.0) : (double)sh.P[0][i * kLd + k];
-      double rk = sh.ring[(J % (BB + 1)) * kT + k];
+      const double zk = sh.ring[(J % (BB + 1)) * kT + k];   // z(J), final
       R* Lgd = Lg + ((size_t)sl * (BB + 1)) * 256;
 #pragma unroll
       for (int p = 0; p < kT; ++p) {
@@ -632,29 +636,37 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
         const double rdp = rcp_nr(dp);
         if (k == p) dmine = dp;
         const double m = v[p] * rdp;             // A lanes: L[k][p] = A[p][k] / D_p (symmetry)
-        const double rp = lane_bcast(rk, p);
-        if (k > p) rk -= m * rp;
 #pragma unroll
         for (int i = p + 1; i < kT; ++i) v[i] -= lane_bcast(v[i], p) * m;
         if (xl && lane < 32) {                   // row p of X is final
           sh.T[k * kLd + p] = (R)(v[p] * rdp);   // T[k][p] = X[p][k] / D_p
-          Lgd[p * kT + k] = (R)v[p];
+          sh.X[p * kLd + k] = (R)v[p];
         }
       }
       if (lane < kT) {
         sh.Dv[k] = dmine;
-        sh.rD[k] = rcp_nr(dmine);
         Dg[(size_t)sl * kT + k] = dmine;
-        sh.yJ[k] = rk;
-        Y[(size_t)sl * kT + k] = rk;
+        sh.yJ[k] = zk;
+        Y[(size_t)sl * kT + k] = zk;
       }
       if (lane == 0 && nonpos) sh.flag[0] = 1;
+      // A^{-1} = T X (one wavefront; T is overwritten only after every lane
+      // has read its operands, which the product's result depends on)
+      V ai = V{0, 0, 0, 0};
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq)
+        ai = Mfma<R>::mma(sh.T[li * kLd + 4 * qq + lk], sh.X[(4 * qq + lk) * kLd + li], ai);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        sh.T[Mfma<R>::row(lk, e) * kLd + li] = ai[e];
+        Lgd[Mfma<R>::row(lk, e) * kT + li] = ai[e];
+      }
     } else if (w == 1 && lane < kT) {
       enter_row(J + BB + 1);           // entering block row J+BB+1
     }
     lds_barrier();
 
-    // (c) panel solve L(J+d, J) = S(J+d, J) T for d >= 1
+    // (c) panel solve M(J+d) = S(J+d, J) A^{-1} for d >= 1
 #pragma unroll
     for (int s = 0; s < SPW; ++s) {
       if (sd[s] < 1) continue;
@@ -668,11 +680,9 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
         res = Mfma<R>::mma(av, bv, res);
       }
       R* Lgd = Lg + ((size_t)sl * (BB + 1) + d) * 256;
-      const R dl = -(R)sh.Dv[li];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         sh.P[d][Mfma<R>::row(lk, e) * kLd + li] = res[e];
-        sh.PD[d][Mfma<R>::row(lk, e) * kLd + li] = dl * res[e];
         Lgd[Mfma<R>::row(lk, e) * kT + li] = res[e];
       }
     }
@@ -738,34 +748,43 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
 }
 
 // ------------------------------------------------------------------ solves
-// forward substitution y = L^{-1} rin with the stored factor (of the whole
-// matrix, or of the part PT of its two-sided form: a top or bottom part
+// The stored factor of panel J holds A_JJ^{-1} (block 0) and M(J+d) =
+// L(J+d, J) L_JJ^{-1} (blocks d = 1..BB); Y holds z = L y.
+//
+// Forward substitution z(J+d) -= M(J+d) z(J) on the right-hand side rin (the
+// whole matrix, or the part PT of its two-sided form: a top or bottom part
 // exports its update of the separator's right-hand side, the separator's
-// sweep starts from both).  Threads t < 16*BB own row (t % 16) of block
-// L(J+1+t/16, J); threads 16*BB..16*BB+15 own a row of L_JJ^{-1}; each keeps
-// its 16 values.  Both sweeps keep the loads of the next few panels (kFwdDepth,
-// back_depth) in flight: a stage is refilled right after its step, every load is in
+// sweep starts from both).  Thread t < 16*BB owns row t % 16 of M(J+1+t/16)
+// and updates that row of the window; the thread of d = BB starts its row
+// (block row J+BB enters) from the right-hand side.  One barrier per panel
+// step: step J reads only z(J), which the previous step's barrier made final,
+// and writes the rows J+1..J+BB.
+//
+// Both sweeps keep the loads of the next few panels (kFwdDepth, kBackDepth)
+// in flight: a stage is refilled right after its step, every load is in
 // bounds and unconditional (values a step does not need are masked where they
 // are used), so each step waits only for the stage it consumes and the HBM
 // latency overlaps the dependent chain of the steps in between.
 template <int BB, int NW, typename R>
 __device__ __attribute__((always_inline)) void forward_sweep(
     const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* rin, double* Y, const Part& PT) {
-  static_assert(NW * kWave >= kT * (BB + 1), "forward sweep needs 16*(BB+1) threads");
+  static_assert(NW * kWave >= kT * BB, "forward sweep needs 16*BB threads");
   const R* Lg = (const R*)(C.ws + WL.L);
   // (fresh: the thread-derived offsets below are formed inside each sweep,
   // not hoisted into registers held across a caller's refinement loop)
   const int t = fresh_v(threadIdx.x);
-  const bool offd = t < kT * BB, diag = t >= kT * BB && t < kT * (BB + 1);
-  // threads past 16*(BB+1) load (and never use) a row of block 0
-  const int d = offd ? 1 + t / kT : 0, a = offd ? t % kT : (t - kT * BB) & (kT - 1);
+  const bool offd = t < kT * BB;
+  // threads past 16*BB load (and never use) a row of block 1
+  const int d = offd ? 1 + t / kT : 1, a = t % kT;
   const double* sr_in = (const double*)(C.ws + WL.sepr);
   for (int i = t; i < (BB + 1) * kT; i += NW * kWave) {
     const int I = i / kT, aa = i - I * kT;
-    sh.ring[i] = PT.kind == kSep ? (I < BB ? sep_rhs<BB>(sr_in, I, aa) : 0.0) : part_rhs(C, rin, PT, I, aa);
+    // rows 0..BB-1; row BB enters at step 0
+    sh.ring[i] = I >= BB ? 0.0
+                         : (PT.kind == kSep ? sep_rhs<BB>(sr_in, I, aa) : part_rhs(C, rin, PT, I, aa));
   }
-  // one pipeline stage: this thread's row of its block of panel J and the
-  // right-hand side entry of the block row that enters after step J
+  // one pipeline stage: this thread's row of M(J+d) and the right-hand side
+  // entry of block row J+BB (the row that enters at step J)
   struct Stage {
     R l[kT];
     double r;
@@ -777,29 +796,23 @@ __device__ __attribute__((always_inline)) void forward_sweep(
     const R* src = Lg + ((size_t)part_slot(C, PT, Jc) * (BB + 1) + d) * 256 + a * kT;
 #pragma unroll
     for (int c = 0; c < kT; ++c) s.l[c] = src[c];
-    const long ri = part_rhs_index(C, PT, Jc + BB + 1, t & (kT - 1));
+    const long ri = part_rhs_index(C, PT, Jc + BB, a);
     s.r = rin[ri < 0 ? 0 : ri];
   };
   auto step = [&](int J, const Stage& s) {
-    if (diag) {
-      const double* rJ = &sh.ring[(J % (BB + 1)) * kT];
-      double y = 0.0;
-#pragma unroll
-      for (int c = 0; c < kT; ++c) y += (double)s.l[c] * rJ[c];
-      sh.yJ[a] = y;
-      Y[(size_t)part_slot(C, PT, J) * kT + a] = y;
-    }
-    lds_barrier();
+    const double* zJ = &sh.ring[(J % (BB + 1)) * kT];
+    if (t < kT) Y[(size_t)part_slot(C, PT, J) * kT + t] = zJ[t];
     if (offd && J + d < PT.rows) {
       double sum = 0.0;
 #pragma unroll
-      for (int c = 0; c < kT; ++c) sum += (double)s.l[c] * sh.yJ[c];
-      sh.ring[((J + d) % (BB + 1)) * kT + a] -= sum;
+      for (int c = 0; c < kT; ++c) sum += (double)s.l[c] * zJ[c];
+      double* zr = &sh.ring[((J + d) % (BB + 1)) * kT + a];
+      if (d == BB)
+        *zr = (part_rhs_index(C, PT, J + BB, a) >= 0 ? s.r : 0.0) - sum;   // (the slot of row J-1)
+      else
+        *zr -= sum;
     }
     lds_barrier();
-    // (row J's slot takes the entering row; the next step reads it only
-    // after its first barrier, so no barrier is needed here)
-    if (t < kT) sh.ring[(J % (BB + 1)) * kT + t] = part_rhs_index(C, PT, J + BB + 1, t) >= 0 ? s.r : 0.0;
   };
   if (PT.steps > 0) {
     // stages filled in the order the loop refills them, so the wait before
@@ -810,12 +823,14 @@ __device__ __attribute__((always_inline)) void forward_sweep(
       __builtin_amdgcn_sched_barrier(0);
     }
     lds_barrier();
+    // whole rounds of kFwdDepth steps (one loop exit, which keeps the
+    // compiler's wait before each step to that step's stage); steps past the
+    // last panel are skipped
     for (int J0 = 0; J0 < PT.steps; J0 += kFwdDepth) {
 #pragma unroll
       for (int b = 0; b < kFwdDepth; ++b) {
         const int J = J0 + b;
-        if (J >= PT.steps) break;
-        step(J, st[b]);
+        if (J < PT.steps) step(J, st[b]);
         load(J + kFwdDepth, st[b]);
       }
     }
@@ -828,14 +843,15 @@ __device__ __attribute__((always_inline)) void forward_sweep(
   __syncthreads();            // Y visible to every wavefront
 }
 
-// backward substitution x = L^{-T} D^{-1} Y; x is written in canonical row
-// order.  Thread (c = t % 16, g = t / 16) accumulates the (d, a) pairs
-// pq = g, g + NG, ... of sum_{d,a} L(J+d,J)[a][c] x_{J+d}[a] and holds one
-// element of L_JJ^{-1}.  Panels jhi down to jlo; blocks at rows >= nbr are
-// absent.  rev: the bottom part's reversed coordinates (panel J stored as
-// block NB-1-J).  keep_ring: the window already holds x of rows
-// jhi+1 .. jhi+BB.  Rows are written to xout (canonical order, plus addlam
-// when given) only with write_x.
+// backward substitution x(J) = A_JJ^{-1} z(J) - sum_d M(J+d)^T x(J+d); x is
+// written in canonical row order.  Thread (c = t % 16, g = t / 16) accumulates
+// the (d, a) pairs pq = g, g + NG, ... (d = pq / 16, a = pq % 16) of
+// sum_a A^{-1}[a][c] z[a] - sum_{d >= 1, a} M(J+d)[a][c] x(J+d)[a], taking
+// z[a] of its d = 0 pair from the stage; lanes 0..15 add the NG partial sums.
+// Panels jhi down to jlo; blocks at rows >= nbr are absent.  rev: the bottom
+// part's reversed coordinates (panel J stored as block NB-1-J).  keep_ring:
+// the window already holds x of rows jhi+1 .. jhi+BB.  Rows are written to
+// xout (canonical order, plus addlam when given) only with write_x.
 struct BackRange {
   int jhi, jlo, nbr;
   bool rev, keep_ring, write_x;
@@ -847,11 +863,11 @@ __device__ __attribute__((always_inline)) void backward_sweep(
     const Ctx& C, const WsLayout& WL, BandShared<BB, NW, R>& sh, const double* Y, double* xout,
     const BackRange& BR) {
   constexpr int NT = NW * kWave;
-  constexpr int NG = NT / kT;                       // 16-thread groups
-  constexpr int NPQ = (BB * kT + NG - 1) / NG;      // (d, a) pairs per thread
-  constexpr int kBackDepth = back_depth(BB);
+  constexpr int NG = NT / kT;                            // 16-thread groups
+  constexpr int NP = (BB + 1) * kT;                      // (d, a) pairs
+  constexpr int NPQ = (NP + NG - 1) / NG;                // pairs per thread
+  static_assert(NG >= kT, "the d = 0 pairs are every thread's first");
   const R* Lg = (const R*)(C.ws + WL.L);
-  const double* Dg = (const double*)(C.ws + WL.Dg);
   // (fresh: the thread-derived offsets below are formed inside each sweep,
   // not hoisted into registers held across a caller's refinement loop)
   const int t = fresh_v(threadIdx.x);
@@ -859,23 +875,20 @@ __device__ __attribute__((always_inline)) void backward_sweep(
   if (!BR.keep_ring)
     for (int i = t; i < (BB + 1) * kT; i += NT) sh.ring[i] = 0.0;
   // element offsets of the thread's (d, a) pairs inside a panel's blocks; a
-  // spare pair (past BB*16) reads an entry it does not use
+  // spare pair (past the last) reads an entry it does not use
   unsigned off[NPQ];
 #pragma unroll
   for (int i = 0; i < NPQ; ++i) {
-    int pq = grp + NG * i;
-    pq = pq < BB * kT ? pq : BB * kT - 1;
-    const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
-    off[i] = (unsigned)(d * 256 + a * kT + cc);
+    const int pq = grp + NG * i < NP ? grp + NG * i : NP - 1;
+    off[i] = (unsigned)((pq / kT) * 256 + (pq % kT) * kT + cc);
   }
-  // one pipeline stage: the thread's L entries of panel J, its element of
-  // L_JJ^{-1}, and for row J*16 + (t % 16): y, D, the canonical index (-1
-  // past the last row) and the multiplier to add, read before the row is
-  // written (addlam may be xout itself)
+  // one pipeline stage: the thread's entries of panel J, z[g % 16] of its
+  // d = 0 pair, and for row J*16 + (t % 16) the canonical index (-1 past the
+  // last row) and the multiplier to add, read before the row is written
+  // (addlam may be xout itself)
   struct Stage {
     R l[NPQ];
-    R dg;
-    double y, dd, al;
+    double zz, al;
     int ci;
   };
   Stage st[kBackDepth];
@@ -886,9 +899,7 @@ __device__ __attribute__((always_inline)) void backward_sweep(
     const R* base = Lg + (size_t)sl * (BB + 1) * 256;
 #pragma unroll
     for (int i = 0; i < NPQ; ++i) s.l[i] = base[off[i]];
-    s.dg = base[t & 255];
-    s.y = Y[sl * kT + cc];
-    s.dd = Dg[sl * kT + cc];
+    s.zz = Y[sl * kT + (grp & 15)];
     const int r = BR.rev ? C.M - 1 - (Jc * kT + cc) : Jc * kT + cc;
     int ci = -1;
     if (r < C.m) {
@@ -899,49 +910,46 @@ __device__ __attribute__((always_inline)) void backward_sweep(
     s.al = alsrc[ci < 0 ? 0 : ci];
   };
   auto step = [&](int J, const Stage& s) {
-    const double yd = s.y / s.dd;                 // lanes < 16 use it
     const int jm = J % (BB + 1);
     double sum = 0.0;
 #pragma unroll
     for (int i = 0; i < NPQ; ++i) {
+      // only the first pair can have d = 0 (pq >= NG >= 16 after it).  Rows
+      // at or past nbr need no mask: their window entries are zero (never
+      // written) and their stored blocks are zero.  A spare pair's entry is
+      // masked in the register, so every window read is unconditional.
       const int pq = grp + NG * i;
-      const int d = 1 + pq / kT, a = pq - (d - 1) * kT;
-      const int slot = jm + d > BB ? jm + d - (BB + 1) : jm + d;
-      const double v = (double)s.l[i] * sh.ring[slot * kT + a];
-      sum += (pq < BB * kT && J + d < BR.nbr) ? v : 0.0;
+      const int d = pq / kT, a = pq % kT;
+      const int dd = d <= BB ? d : BB;
+      const int slot = jm + dd > BB ? jm + dd - (BB + 1) : jm + dd;
+      const double xv = sh.ring[slot * kT + a];
+      const double lv = pq < NP ? (double)s.l[i] : 0.0;
+      sum += lv * (i == 0 && d == 0 ? s.zz : -xv);
     }
     sh.part[t] = sum;
-    if (t < 256) sh.Xw[(t >> 4) * kLd + (t & 15)] = (double)s.dg;
     lds_barrier();
     if (t < kT) {
-      // lanes 0..15 of wavefront 0: entry t of y_J minus the sum, then
-      // x = L_JJ^{-T} of it with entry c2 read from lane c2 (no barrier)
-      double acc = 0.0;
-      for (int q = 0; q < NG; ++q) acc += sh.part[q * kT + t];
-      const double yv = yd - acc;
       double x = 0.0;
-#pragma unroll
-      for (int c2 = 0; c2 < kT; ++c2) x += sh.Xw[c2 * kLd + t] * lane_bcast(yv, c2);   // L_JJ^{-T}
+      for (int q = 0; q < NG; ++q) x += sh.part[q * kT + t];
       sh.ring[jm * kT + t] = x;
       if (BR.write_x && s.ci >= 0) xout[s.ci] = BR.addlam ? x + s.al : x;
     }
     lds_barrier();
   };
   if (BR.jhi >= BR.jlo) {
-    // stages filled in the order the loop refills them, so the wait before
-    // each step covers that stage's loads only
+    // stages filled in the order the loop refills them (as in the forward sweep)
 #pragma unroll
     for (int b = 0; b < kBackDepth; ++b) {
       load(BR.jhi - b, st[b]);
       __builtin_amdgcn_sched_barrier(0);
     }
     lds_barrier();
+    // whole rounds of kBackDepth steps (one loop exit, as in the forward sweep)
     for (int J0 = BR.jhi; J0 >= BR.jlo; J0 -= kBackDepth) {
 #pragma unroll
       for (int b = 0; b < kBackDepth; ++b) {
         const int J = J0 - b;
-        if (J < BR.jlo) break;
-        step(J, st[b]);
+        if (J >= BR.jlo) step(J, st[b]);
         load(J - kBackDepth, st[b]);
       }
     }
