@@ -64,12 +64,26 @@ extern "C" {
  *                   Solved in the orthonormal real Fourier basis of each
  *                   frame; PREC_MIXED runs the same FP64 arithmetic (the
  *                   family has no band factorization to lower).
+ * SNAP_BURGERS_BC   boundary conditions and mass of the paper's first Burgers
+ *                   constraint regime (Appendix A, Burgers problem: Dirichlet
+ *                   condition on the left boundary, mass, Neumann condition on
+ *                   the right boundary; Appendix D discretizations).  Grid
+ *                   x_i = i*dx, 3 <= Nx <= 512.  Rows, canonical order, for
+ *                   k = 0..Nt-1 each: u_0^k - u_L; then dx*sum_i u_i^k - m0;
+ *                   then (u_{Nx-1}^k - u_{Nx-2}^k)/dx.  aux = [u_L, m0].  The
+ *                   rows are linear and per time step, so each step is
+ *                   projected in closed form (3 x 3 Schur matrix); further
+ *                   Newton steps only correct rounding.  No workspace; PREC_MIXED
+ *                   runs the same FP64 arithmetic.  The adjoint is the
+ *                   projection of the upstream gradient onto the rows' null
+ *                   space.
  */
 enum snap_family {
   SNAP_MASS_IC = 1,
   SNAP_FISHER_KPP = 2,
   SNAP_BURGERS_LF = 3,
-  SNAP_DIFF2D_ENERGY = 4
+  SNAP_DIFF2D_ENERGY = 4,
+  SNAP_BURGERS_BC = 5
 };
 
 enum snap_precision {

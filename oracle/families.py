@@ -21,13 +21,17 @@ Pins (tests/test_oracle_pins.py):
   diff2d      consistency with the heat equation on a decaying Fourier mode;
               single energy row = sphere projection (closed form); J/Hessian
               vs FD.
+  burgers_bc  dense affine projection (closed form); a discrete field built to
+              meet the boundary conditions and the mass is a fixed point; the
+              Neumann row vanishes on fields flat at the right end and the
+              Dirichlet row reads the left end only.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
 
-MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY = 1, 2, 3, 4
+MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY, BURGERS_BC = 1, 2, 3, 4, 5
 
 
 def _vid1(nx, k, i):
@@ -291,8 +295,62 @@ class Diff2DEnergy:
         return {"residual": r[:k], "energy": r[k:]}
 
 
+class BurgersBC:
+    """Boundary rows and global mass of the paper's first Burgers constraint
+    regime (Appendix A, Burgers problem: the Dirichlet condition on the left
+    boundary, the mass constraint and the Neumann condition on the right
+    boundary), discretized as in Appendix D: the mass by the Riemann sum
+    m(t_k) = sum_i u_i^k dx, the Neumann condition by the one-sided difference
+    (u_{Nx-1}^k - u_{Nx-2}^k) / dx at the right end.  Grid x_i = i dx on
+    [0, 1], i = 0..Nx-1, dx = 1 / (Nx - 1); one row of each kind per time step
+    k = 0..Nt-1.
+
+    Canonical rows (by kind, then step):
+      Dirichlet  u_0^k - u_L                          k = 0..Nt-1
+      mass       dx sum_i u_i^k - m0                  k = 0..Nt-1
+      Neumann    (u_{Nx-1}^k - u_{Nx-2}^k) / dx       k = 0..Nt-1
+    All rows are linear: the Hessian of lam^T h is zero.  Nx >= 3 keeps the
+    three rows of a step independent.
+    """
+    types = ("dirichlet", "mass", "neumann")
+
+    def __init__(self, nx, nt, dx, u_left, m0):
+        self.nx, self.nt = int(nx), int(nt)
+        if self.nx < 3:
+            raise ValueError("Burgers boundary rows need nx >= 3")
+        self.dx = float(dx)
+        self.u_left, self.m0 = float(u_left), float(m0)
+        self.n = self.nx * self.nt
+        self.m = 3 * self.nt
+
+    def h(self, u):
+        U = u.reshape(self.nt, self.nx)
+        dirichlet = U[:, 0] - self.u_left
+        mass = self.dx * U.sum(axis=1) - self.m0
+        neumann = (U[:, -1] - U[:, -2]) / self.dx
+        return np.concatenate([dirichlet, mass, neumann])
+
+    def jac(self, u):
+        rows, cols, vals = [], [], []
+        nt, nx = self.nt, self.nx
+        for k in range(nt):
+            rows.append(k); cols.append(_vid1(nx, k, 0)); vals.append(1.0)
+            for i in range(nx):
+                rows.append(nt + k); cols.append(_vid1(nx, k, i)); vals.append(self.dx)
+            rows.append(2 * nt + k); cols.append(_vid1(nx, k, nx - 1)); vals.append(1.0 / self.dx)
+            rows.append(2 * nt + k); cols.append(_vid1(nx, k, nx - 2)); vals.append(-1.0 / self.dx)
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.m, self.n))
+
+    def hess(self, u, lam):
+        return sp.csr_matrix((self.n, self.n))
+
+    def split(self, r):
+        nt = self.nt
+        return {"dirichlet": r[:nt], "mass": r[nt:2 * nt], "neumann": r[2 * nt:]}
+
+
 FAMILIES = {MASS_IC: MassIC, FISHER_KPP: FisherKPP, BURGERS_LF: BurgersLF,
-            DIFF2D_ENERGY: Diff2DEnergy}
+            DIFF2D_ENERGY: Diff2DEnergy, BURGERS_BC: BurgersBC}
 
 
 def family_of(sample, **kw):
@@ -307,6 +365,8 @@ def family_of(sample, **kw):
     if f == DIFF2D_ENERGY:
         return Diff2DEnergy(sample.nx, sample.ny, sample.nt, sample.dt, sample.dx,
                             sample.p0, sample.aux)
+    if f == BURGERS_BC:
+        return BurgersBC(sample.nx, sample.nt, sample.dx, sample.aux[0], sample.aux[1])
     raise ValueError(f"unknown family {f}")
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsnap.so")
-SOURCES = ["snap_api.cpp", "snap_slab.hip", "snap_slab_wide.hip", "snap_band.hip", "snap_spec.hip", "snap_flow.hip"]
+SOURCES = ["snap_api.cpp", "snap_slab.hip", "snap_slab_wide.hip", "snap_band.hip", "snap_spec.hip", "snap_flow.hip", "snap_bc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

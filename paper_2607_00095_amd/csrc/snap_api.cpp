@@ -33,6 +33,9 @@ int band_group_class(int cls, int min_nb, int count, int ncu);
 bool spec_supported(int nx, int ny, int nt);
 size_t spec_workspace_bytes(int nx, int nt);
 int spec_launch(const KernelArgs& a, hipStream_t st);
+bool bc_supported(int nx, int ny, int nt);
+int bc_class(int nx);
+int bc_launch(const KernelArgs& a, int cls, hipStream_t st);
 }  // namespace snap
 
 using namespace snap;
@@ -72,8 +75,9 @@ void* scratch_ptr(int device) {
 
 // Samples sharing one kernel instantiation (shapes may differ: every kernel
 // reads its sample's shape from the descriptor).  `kind` 0 = slab rows,
-// 1 = banded, 2 = spectral (2D diffusion + energy); `cls` = instantiation index; ids sorted by decreasing cost so
-// the longest samples start first.
+// 1 = banded, 2 = spectral (2D diffusion + energy), 3 = boundary rows (Burgers
+// boundary conditions + mass); `cls` = instantiation index; ids sorted by
+// decreasing cost so the longest samples start first.
 struct Group {
   int kind, cls;
   double cost = 0.0;
@@ -138,6 +142,7 @@ int64_t rows_of(const snap_sample_desc& d) {
     case SNAP_FISHER_KPP: return (int64_t)d.nx + d.nt - 1;
     case SNAP_BURGERS_LF: return (int64_t)d.nx * (d.nt - 1);
     case SNAP_DIFF2D_ENERGY: return (int64_t)d.nx * d.ny * (d.nt - 1) + d.nt;
+    case SNAP_BURGERS_BC: return 3 * (int64_t)d.nt;
     default: return -1;
   }
 }
@@ -147,6 +152,7 @@ int64_t aux_of(const snap_sample_desc& d) {
     case SNAP_MASS_IC: return d.nx + 1;
     case SNAP_FISHER_KPP: return d.nx;
     case SNAP_DIFF2D_ENERGY: return d.nt;
+    case SNAP_BURGERS_BC: return 2;
     default: return 0;
   }
 }
@@ -398,6 +404,10 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
       cls = (d.dt > 0.0 && d.dx > 0.0 && d.p0 >= 0.0 && spec_supported(d.nx, d.ny, d.nt)) ? 0 : -1;
       if (cls == 0) need = spec_workspace_bytes(d.nx, d.nt);
       cost[s] = (double)d.nx * d.ny * 16.0 * 40.0;
+    } else if (d.family == SNAP_BURGERS_BC) {
+      kind = 3;
+      cls = (d.dx > 0.0 && bc_supported(d.nx, d.ny, d.nt)) ? bc_class(d.nx) : -1;
+      cost[s] = (double)d.nx * d.nt;
     }
     if (cls < 0) { free_plan(p); return SNAP_EUNSUPPORTED; }
     p->ws_off[s] = (int64_t)ws;
@@ -550,6 +560,7 @@ int launch_group_cls(const snap_plan_s& p, KernelArgs a, const Group& g, int cls
   a.count = (int32_t)g.ids.size();
   a.tab = p.d_tab;
   if (g.kind == 2) return spec_launch(a, st);
+  if (g.kind == 3) return bc_launch(a, cls, st);
   return g.kind == 0 ? slab_launch(a, cls, mixed, st) : band_launch(a, cls, mixed, st);
 }
 }  // namespace
@@ -698,8 +709,8 @@ int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed) {
     const Group& g = plan->groups[i];
     char line[192];
     std::snprintf(line, sizeof(line), "group %zu: %s class %d, %d wavefronts per workgroup%s, %zu samples\n",
-                  i, g.kind == 0 ? "slab" : (g.kind == 1 ? "band" : "spectral"), g.cls,
-                  g.kind == 0 ? slab_waves(g.cls) : (g.kind == 1 ? band_waves(g.cls) : 8),
+                  i, g.kind == 0 ? "slab" : (g.kind == 1 ? "band" : (g.kind == 2 ? "spectral" : "boundary-row")), g.cls,
+                  g.kind == 0 ? slab_waves(g.cls) : (g.kind == 1 ? band_waves(g.cls) : (g.kind == 2 ? 8 : 16)),
                   g.kind == 1 && band_sides(g.cls) == 2 ? ", two-sided factorization" : "", g.ids.size());
     t += line;
   }

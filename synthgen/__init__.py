@@ -18,6 +18,9 @@ Families (the integer codes match the C header):
                  smooth Lax-Friedrichs flux (Appendix D flux residual)
   4  DIFF2D_ENERGY  implicit 2D diffusion residuals + per-frame quadratic
                  invariant (Appendix A Navier-Stokes analogue)
+  5  BURGERS_BC  Dirichlet row on the left boundary, mass row and Neumann row
+                 on the right boundary per time step (Appendix A, the first
+                 Burgers regime; Appendix D discretizations)
 
 Every field is float64.  Layout of one sample: time slab major, then y, then x
 (x fastest), which is the paper's flattening of the space-time grid
@@ -34,8 +37,9 @@ F1_MASS_IC = 1
 F2_FISHER_KPP = 2
 F3_BURGERS_LF = 3
 F4_DIFF2D_ENERGY = 4
+F5_BURGERS_BC = 5
 
-FAMILY_NAMES = {1: "mass_ic", 2: "fisher_kpp", 3: "burgers_lf", 4: "diff2d_energy"}
+FAMILY_NAMES = {1: "mass_ic", 2: "fisher_kpp", 3: "burgers_lf", 4: "diff2d_energy", 5: "burgers_bc"}
 
 
 def n_rows(family: int, nx: int, ny: int, nt: int) -> int:
@@ -46,6 +50,8 @@ def n_rows(family: int, nx: int, ny: int, nt: int) -> int:
         return nx * (nt - 1)
     if family == F4_DIFF2D_ENERGY:
         return (nt - 1) * nx * ny + nt
+    if family == F5_BURGERS_BC:
+        return 3 * nt
     raise ValueError(f"unknown family {family}")
 
 
@@ -58,6 +64,8 @@ def n_aux(family: int, nx: int, ny: int, nt: int) -> int:
         return 0
     if family == F4_DIFF2D_ENERGY:
         return nt              # E[nt]
+    if family == F5_BURGERS_BC:
+        return 2               # u_L, m0
     raise ValueError(f"unknown family {family}")
 
 
@@ -203,6 +211,47 @@ def _draw_f3(rng, nx, nt, dt=1e-3, nu=0.01, alpha=1.0, noise=0.02) -> Sample:
                   uhat=traj, aux=np.zeros(0))
 
 
+def _godunov_bc_trajectory(u0, nt, dt, dx, u_left):
+    """Inviscid Burgers by Godunov's finite-volume method with the left
+    boundary held at u_left and a zero-gradient right boundary, saved every dt
+    (CFL-limited substeps); input synthesis only."""
+    def flux(a, b):
+        # Godunov flux of f(u) = u^2 / 2 between states a (left) and b (right)
+        return np.maximum(0.5 * np.maximum(a, 0.0) ** 2, 0.5 * np.minimum(b, 0.0) ** 2)
+    traj = np.empty((nt, u0.size))
+    u = u0.copy()
+    u[0] = u_left
+    traj[0] = u
+    for k in range(1, nt):
+        t = 0.0
+        while t < dt - 1e-15:
+            h = min(dt - t, 0.45 * dx / max(np.abs(u).max(), 1e-12))
+            ghost = np.concatenate([[u_left], u, [u[-1]]])
+            f = flux(ghost[:-1], ghost[1:])            # interfaces i-1/2, i = 0..nx
+            u = u - (h / dx) * (f[1:] - f[:-1])
+            u[0] = u_left
+            t += h
+        traj[k] = u
+    return traj
+
+
+def _draw_f5(rng, nx, nt, noise=0.05) -> Sample:
+    # the paper's Burgers-BC setting: front 1 / (1 + exp((x - p) / eps)),
+    # eps = 0.02, p ~ U(0.2, 0.8); left boundary value u_bc ~ U(0, 1); grid
+    # with both ends on [0, 1] and t in [0, 1]
+    dx = 1.0 / (nx - 1)
+    dt = 1.0 / max(nt - 1, 1)
+    x = np.arange(nx) * dx
+    p = rng.uniform(0.2, 0.8)
+    u_left = rng.uniform(0.0, 1.0)
+    u0 = 1.0 / (1.0 + np.exp((x - p) / 0.02))
+    m0 = float(dx * u0.sum())
+    clean = _godunov_bc_trajectory(u0, nt, dt, dx, u_left)
+    uhat = clean + noise * rng.standard_normal(clean.shape)
+    return Sample(F5_BURGERS_BC, nx, 1, nt, dt=dt, dx=dx, uhat=uhat,
+                  aux=np.array([u_left, m0]))
+
+
 def _draw_f4(rng, n, nt, dt=0.01, noise=0.05) -> Sample:
     kappa = rng.uniform(0.01, 0.1)
     h = 1.0 / n
@@ -249,6 +298,11 @@ def burgers_batch(batch=512, nx=128, nt=128, dt=1e-3, nu=0.01, alpha=1.0, seed=3
     rng = _rng(seed)
     return Batch([_draw_f3(rng, nx, nt, dt, nu, alpha) for _ in range(batch)],
                  name="burgers_lf").pack()
+
+
+def burgers_bc_batch(batch=512, nx=101, nt=101, seed=6001) -> Batch:
+    rng = _rng(seed)
+    return Batch([_draw_f5(rng, nx, nt) for _ in range(batch)], name="burgers_bc").pack()
 
 
 def diff2d_batch(batch=128, n=64, nt=16, dt=0.01, seed=4001) -> Batch:
@@ -301,6 +355,8 @@ CONFIGS = {
     # where float64 no longer determines the projection)
     "diff2d_energy": dict(fn=diff2d_batch, kw=dict(batch=128, n=64, nt=6, seed=4001)),
     "ragged": dict(fn=ragged_batch, kw=dict(batch=1024, seed=5001)),
+    # the paper's first Burgers regime (boundary rows + mass) on its 101 x 101 grid
+    "burgers_bc": dict(fn=burgers_bc_batch, kw=dict(batch=512, nx=101, nt=101, seed=6001)),
 }
 
 
