@@ -710,7 +710,7 @@ int snap_plan_describe(snap_plan plan, char* buf, size_t len, size_t* needed) {
     char line[192];
     std::snprintf(line, sizeof(line), "group %zu: %s class %d, %d wavefronts per workgroup%s, %zu samples\n",
                   i, g.kind == 0 ? "slab" : (g.kind == 1 ? "band" : (g.kind == 2 ? "spectral" : "boundary-row")), g.cls,
-                  g.kind == 0 ? slab_waves(g.cls) : (g.kind == 1 ? band_waves(g.cls) : (g.kind == 2 ? 8 : 16)),
+                  g.kind == 0 ? slab_waves(g.cls) : (g.kind == 1 ? band_waves(g.cls) : 8),
                   g.kind == 1 && band_sides(g.cls) == 2 ? ", two-sided factorization" : "", g.ids.size());
     t += line;
   }

@@ -12,26 +12,43 @@
 // corrects the rounding of the first.  The adjoint projects the upstream
 // gradient onto null(A): grad = g - A^T S^{-1} A g.
 //
-// Layout: one workgroup of kBcWaves wavefronts per sample; wavefront w takes
-// slabs w, w + kBcWaves, ...; lane l holds x = l, l + 64, ... of a slab in
-// XR registers (the class: 64 XR >= nx, XR in {1, 2, 4, 8}), so the slab is
-// read once from HBM and written once.  Every load is unconditional (lanes
-// past the slab's end read its last value, masked where used) and up to
-// four of the wavefront's next slabs are in flight while it works on the
-// current one.  The kernel is HBM-bound on compulsory bytes.
+// Layout: one workgroup of kBcWaves wavefronts per sample.  A group of G
+// lanes owns a slab (G = 16, a DPP row, for nx <= 128; G = 64, the whole
+// wavefront, above), lane p of the group holds x = p, p + G, ... in XR
+// registers (G XR >= nx), so a slab is read once from HBM and written once
+// and a wavefront projects 64 / G slabs at a time.  Group sums are DPP row
+// rotations (G = 16) or the wavefront reduction (G = 64); the boundary values
+// are group sums of masked values.  Every load is unconditional (lanes past
+// the slab's end, and groups past the last slab, read valid addresses and are
+// masked where used) and the next kDepth rounds of slabs are in flight while
+// the wavefront works on the current one.  The kernel is HBM-bound on
+// compulsory bytes.
 #include "snap_device.hpp"
 
 namespace snap {
 
 namespace {
 
-constexpr int kBcWaves = 16;
-constexpr int kBcMaxX = 8;        // nx <= 512
+constexpr int kBcWaves = 8;
 
 struct BcRows {
   double dx, rdx, uL, m0, det;     // det = (nx - 1) dx^2 of the upper 2 x 2 block
   int nx;
 };
+
+// sum over the G lanes of a group, the same in every lane of the group
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+  if constexpr (G == 16) {
+    x += dpp_d<0x128, 0xf, true>(x);   // row_ror:8
+    x += dpp_d<0x124, 0xf, true>(x);   // row_ror:4
+    x += dpp_d<0x122, 0xf, true>(x);   // row_ror:2
+    x += dpp_d<0x121, 0xf, true>(x);   // row_ror:1
+    return x;
+  } else {
+    return wave_sum(x);
+  }
+}
 
 // multipliers of one slab's rows from its residual (r_D, r_M, r_N)
 __device__ __forceinline__ void bc_solve(const BcRows& R, double rD, double rM, double rN, double& lD,
@@ -42,56 +59,47 @@ __device__ __forceinline__ void bc_solve(const BcRows& R, double rD, double rM, 
   lN = 0.5 * rN * R.dx * R.dx;
 }
 
-// value at x of a slab held in registers, on every lane (x = lane + 64 j:
-// read from lane x % 64 of register x / 64)
-template <int XR>
-__device__ __forceinline__ double bc_at(const double* v, int x) {
-  double r = v[0];
-#pragma unroll
-  for (int j = 1; j < XR; ++j)
-    if (x >= kWave * j) r = v[j];          // x is uniform: a scalar branch
-  const int l = x & (kWave - 1);
-  const int lo = __builtin_amdgcn_readlane(__double2loint(r), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(r), l);
-  return __hiloint2double(hi, lo);
-}
-
-// residual of one slab held in registers (v[j] = u at x = lane + 64 j; zero
-// past the slab's end): one wavefront sum for the mass, lane reads for the
-// boundary values
-template <int XR>
-__device__ __forceinline__ void bc_residual(const BcRows& R, const double* v, int lane, bool homog,
+// residual of the group's slab held in registers (v[j] = u at x = p + G j;
+// zero past the slab's end)
+template <int G, int XR>
+__device__ __forceinline__ void bc_residual(const BcRows& R, const double* v, int p, bool homog,
                                             double& rD, double& rM, double& rN) {
-  double s = 0.0;
+  double s = 0.0, a = 0.0, bm = 0.0, bl = 0.0;
 #pragma unroll
-  for (int j = 0; j < XR; ++j) s += v[j];
-  s = wave_sum(s);
-  const double a = bc_at<XR>(v, 0), bm = bc_at<XR>(v, R.nx - 2), bl = bc_at<XR>(v, R.nx - 1);
+  for (int j = 0; j < XR; ++j) {
+    const int x = p + G * j;
+    s += v[j];
+    a += x == 0 ? v[j] : 0.0;
+    bm += x == R.nx - 2 ? v[j] : 0.0;
+    bl += x == R.nx - 1 ? v[j] : 0.0;
+  }
+  s = group_sum<G>(s);
+  a = group_sum<G>(a);
+  bm = group_sum<G>(bm);
+  bl = group_sum<G>(bl);
   rD = homog ? a : a - R.uL;
   rM = homog ? R.dx * s : R.dx * s - R.m0;
   rN = (bl - bm) * R.rdx;
 }
 
-// v -= A^T lam on the slab in registers (entries past the slab's end stay 0)
-template <int XR>
-__device__ __forceinline__ void bc_apply(const BcRows& R, double* v, int lane, double lD, double lM, double lN) {
-#pragma unroll
-  for (int j = 0; j < XR; ++j) {
-    const int x = lane + kWave * j;
-    double d = R.dx * lM;
-    if (x == 0) d += lD;
-    if (x == R.nx - 2) d -= lN * R.rdx;
-    if (x == R.nx - 1) d += lN * R.rdx;
-    if (x < R.nx) v[j] -= d;
-  }
+// A^T lam at x
+__device__ __forceinline__ double bc_at(const BcRows& R, int x, double lD, double lM, double lN) {
+  double d = R.dx * lM;
+  if (x == 0) d += lD;
+  if (x == R.nx - 2) d -= lN * R.rdx;
+  if (x == R.nx - 1) d += lN * R.rdx;
+  return d;
 }
 
-template <int XR>
+template <int G, int XR>
 __global__ __launch_bounds__(kBcWaves * kWave) void bc_kernel(KernelArgs A) {
+  constexpr int SPW = kWave / G;                         // slabs a wavefront projects at once
+  constexpr int kDepth = XR <= 2 ? 4 : (XR == 4 ? 2 : 1);
   const int sid = A.order[blockIdx.x];
   const snap_sample_desc D = A.descs[sid];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
+  const int p = lane % G, grp = lane / G;
   __shared__ double red[kBcWaves][3];
   __shared__ int itmax[kBcWaves];
 
@@ -108,77 +116,84 @@ __global__ __launch_bounds__(kBcWaves * kWave) void bc_kernel(KernelArgs A) {
   double* dst = A.backward ? A.grad_uhat : A.u;
   const int max_it = A.opt.max_newton;
 
+  // round i of wavefront w: slabs SPW (w + kBcWaves i) + grp; unconditional
+  // loads (past the last slab: the last slab; past the slab's end: its last
+  // value), masked where used
+  const int rounds = (nt + SPW - 1) / SPW;
+  const int cnt = w < rounds ? (rounds - 1 - w) / kBcWaves + 1 : 0;
+  auto slab_of = [&](int i) { return SPW * (w + kBcWaves * i) + grp; };
+  auto load = [&](int i, double* dstv) {
+    const double* in = src + vo + (int64_t)min(slab_of(i), nt - 1) * nx;
+#pragma unroll
+    for (int j = 0; j < XR; ++j) dstv[j] = in[min(p + G * j, nx - 1)];
+  };
   double hmax = 0.0, smax = 0.0, umax = 0.0;
   int iters = 0, nonfin = 0;
-  // unconditional loads: a slab past the last reads the last, a lane past the
-  // slab's end its last value (never stored; masked in the sums).  Wavefront
-  // w's slabs are k = w + kBcWaves i; kDepth of them are in flight at once
-  // (whole rounds with one loop exit, so each wait covers one slab's loads).
-  constexpr int kDepth = XR <= 2 ? 4 : (XR == 4 ? 2 : 1);
-  auto load = [&](int i, double* dst) {
-    const double* in = src + vo + (int64_t)min(w + kBcWaves * i, nt - 1) * nx;
-#pragma unroll
-    for (int j = 0; j < XR; ++j) dst[j] = in[min(lane + kWave * j, nx - 1)];
-  };
-  const int cnt = w < nt ? (nt - 1 - w) / kBcWaves + 1 : 0;   // this wavefront's slabs
   double stg[kDepth][XR];
 #pragma unroll
   for (int b = 0; b < kDepth; ++b) load(b, stg[b]);
+  // whole rounds of kDepth stages with one loop exit, so each wait covers one
+  // stage's loads
   for (int i0 = 0; i0 < cnt; i0 += kDepth) {
 #pragma unroll
     for (int b = 0; b < kDepth; ++b) {
       const int i = i0 + b;
       if (i < cnt) {
-        const int k = w + kBcWaves * i;
+        const int k = slab_of(i);
+        const bool live = k < nt;
         double v[XR], v0[XR];
 #pragma unroll
         for (int j = 0; j < XR; ++j) {
-          const int x = lane + kWave * j;
-          v[j] = x < nx ? stg[b][j] : 0.0;
+          v[j] = (live && p + G * j < nx) ? stg[b][j] : 0.0;
           v0[j] = v[j];
           umax = fmax(umax, fabs(v[j]));
           nonfin |= !finite(v[j]);
         }
         double LD = 0.0, LM = 0.0, LN = 0.0, rD, rM, rN;
-        bc_residual<XR>(R, v, lane, A.backward != 0, rD, rM, rN);
+        bc_residual<G, XR>(R, v, p, A.backward != 0, rD, rM, rN);
+        double rmax = live ? fmax(fabs(rD), fmax(fabs(rM), fabs(rN))) : 0.0;
         int it = 0;
-        // Newton steps on the slab (the first solves it; later ones correct rounding)
-        while (it < max_it && (it == 0 || fmax(fabs(rD), fmax(fabs(rM), fabs(rN))) > A.opt.tol_h)) {
+        // Newton steps on the slabs (the first solves them; later ones correct
+        // rounding), while any group of the wavefront is above the tolerance
+        while (it < max_it && (it == 0 || wave_max(rmax) > A.opt.tol_h)) {
           double lD, lM, lN;
           bc_solve(R, rD, rM, rN, lD, lM, lN);
-          bc_apply<XR>(R, v, lane, lD, lM, lN);
+#pragma unroll
+          for (int j = 0; j < XR; ++j) {
+            const int x = p + G * j;
+            if (x < nx) v[j] -= bc_at(R, x, lD, lM, lN);
+          }
           LD += lD; LM += lM; LN += lN;
-          bc_residual<XR>(R, v, lane, A.backward != 0, rD, rM, rN);
+          bc_residual<G, XR>(R, v, p, A.backward != 0, rD, rM, rN);
+          rmax = live ? fmax(fabs(rD), fmax(fabs(rM), fabs(rN))) : 0.0;
           ++it;
         }
         iters = max(iters, it);
-        double* out = dst + vo + (int64_t)k * nx;
-        double st = 0.0;
+        if (live) {
+          double* out = dst + vo + (int64_t)k * nx;
 #pragma unroll
-        for (int j = 0; j < XR; ++j) {
-          const int x = lane + kWave * j;
-          if (x < nx) {
-            out[x] = v[j];
-            // stationarity u - u_hat + A^T lam (forward)
-            double at = R.dx * LM;
-            if (x == 0) at += LD;
-            if (x == nx - 2) at -= LN * R.rdx;
-            if (x == nx - 1) at += LN * R.rdx;
-            st = fmax(st, fabs(v[j] - v0[j] + at));
+          for (int j = 0; j < XR; ++j) {
+            const int x = p + G * j;
+            if (x < nx) {
+              out[x] = v[j];
+              // stationarity u - u_hat + A^T lam
+              smax = fmax(smax, fabs(v[j] - v0[j] + bc_at(R, x, LD, LM, LN)));
+            }
           }
+          if (!A.backward && p == 0) {
+            A.lam[ro + k] = LD;
+            A.lam[ro + nt + k] = LM;
+            A.lam[ro + 2 * nt + k] = LN;
+          }
+          hmax = fmax(hmax, rmax);
         }
-        if (!A.backward && lane == 0) {
-          A.lam[ro + k] = LD;
-          A.lam[ro + nt + k] = LM;
-          A.lam[ro + 2 * nt + k] = LN;
-        }
-        hmax = fmax(hmax, fmax(fabs(rD), fmax(fabs(rM), fabs(rN))));
-        smax = fmax(smax, wave_max(st));
       }
       load(i + kDepth, stg[b]);
     }
   }
   // per-sample stats (forward: status from the final residuals)
+  hmax = wave_max(hmax);
+  smax = wave_max(smax);
   umax = wave_max(umax);
   const double nf = wave_max((double)nonfin);
   if (lane == 0) {
@@ -213,19 +228,25 @@ __global__ __launch_bounds__(kBcWaves * kWave) void bc_kernel(KernelArgs A) {
 
 }  // namespace
 
-bool bc_supported(int nx, int ny, int nt) { return ny == 1 && nx >= 3 && nx <= kWave * kBcMaxX && nt >= 1; }
+bool bc_supported(int nx, int ny, int nt) { return ny == 1 && nx >= 3 && nx <= 512 && nt >= 1; }
 
-// x registers per lane for a slab of nx points
-int bc_class(int nx) { return nx <= kWave ? 1 : nx <= 2 * kWave ? 2 : nx <= 4 * kWave ? 4 : 8; }
+// launch class: lanes per slab and x registers per lane (G = 16 up to
+// nx = 128: 1, 2, 4, 8; G = 64 above: 104 (nx <= 256), 108)
+int bc_class(int nx) {
+  if (nx <= 128) return nx <= 16 ? 1 : nx <= 32 ? 2 : nx <= 64 ? 4 : 8;
+  return nx <= 256 ? 104 : 108;
+}
 
 int bc_launch(const KernelArgs& a, int cls, hipStream_t st) {
   if (a.count <= 0) return 0;
   const dim3 grid(a.count), block(kBcWaves * kWave);
   switch (cls) {
-    case 1: hipLaunchKernelGGL(bc_kernel<1>, grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(bc_kernel<2>, grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(bc_kernel<4>, grid, block, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(bc_kernel<8>, grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((bc_kernel<16, 1>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((bc_kernel<16, 2>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((bc_kernel<16, 4>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((bc_kernel<16, 8>), grid, block, 0, st, a); break;
+    case 104: hipLaunchKernelGGL((bc_kernel<64, 4>), grid, block, 0, st, a); break;
+    case 108: hipLaunchKernelGGL((bc_kernel<64, 8>), grid, block, 0, st, a); break;
     default: return SNAP_EUNSUPPORTED;
   }
   return hipGetLastError() == hipSuccess ? 0 : SNAP_EHIP;
