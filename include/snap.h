@@ -77,13 +77,24 @@ extern "C" {
  *                   runs the same FP64 arithmetic.  The adjoint is the
  *                   projection of the upstream gradient onto the rows' null
  *                   space.
+ * SNAP_BURGERS_GODUNOV  flux-update residuals (Appendix D, Godunov's flux
+ *                   conservation) of Burgers with Godunov's interface flux
+ *                   F(a, b) = max(f(max(a,0)), f(min(b,0))), f = u^2/2, plus a
+ *                   centred viscous term, periodic x.  Rows (k,i), k-major,
+ *                   k = 0..Nt-2: u_i^{k+1} - u_i^k + (dt/dx)(F_{i+1/2} -
+ *                   F_{i-1/2}) - p0*dt/dx^2 (u_{i+1}^k - 2u_i^k + u_{i-1}^k).
+ *                   p0 = nu (0: inviscid).  No aux.  Solved by the banded
+ *                   path of SNAP_BURGERS_LF; the flux is piecewise smooth and
+ *                   Newton steps differentiate the branch that attains the
+ *                   max (ties: the left state's), a semismooth Newton method.
  */
 enum snap_family {
   SNAP_MASS_IC = 1,
   SNAP_FISHER_KPP = 2,
   SNAP_BURGERS_LF = 3,
   SNAP_DIFF2D_ENERGY = 4,
-  SNAP_BURGERS_BC = 5
+  SNAP_BURGERS_BC = 5,
+  SNAP_BURGERS_GODUNOV = 6
 };
 
 enum snap_precision {

@@ -21,6 +21,10 @@ Pins (tests/test_oracle_pins.py):
   diff2d      consistency with the heat equation on a decaying Fourier mode;
               single energy row = sphere projection (closed form); J/Hessian
               vs FD.
+  godunov     an exact steady shock and the sonic expansion give the
+              flux values Riemann's problem fixes; consistency with the
+              inviscid PDE on a smooth one-signed wave; J and the Hessian vs
+              finite differences away from the flux's kinks.
   burgers_bc  dense affine projection (closed form); a discrete field built to
               meet the boundary conditions and the mass is a fixed point; the
               Neumann row vanishes on fields flat at the right end and the
@@ -31,7 +35,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY, BURGERS_BC = 1, 2, 3, 4, 5
+MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY, BURGERS_BC, BURGERS_GODUNOV = 1, 2, 3, 4, 5, 6
 
 
 def _vid1(nx, k, i):
@@ -295,6 +299,96 @@ class Diff2DEnergy:
         return {"residual": r[:k], "energy": r[k:]}
 
 
+class BurgersGodunov:
+    """Local flux-update residuals of Burgers u_t + (u^2/2)_x = nu*u_xx on a
+    periodic grid with Godunov's interface flux (paper Appendix D, Godunov's
+    flux conservation: each row is the mismatch between consecutive steps and
+    one conservative finite-volume update), plus a centred viscous term
+    (nu = 0: the inviscid equation of the paper's Burgers problem).
+
+    Godunov flux of the convex f(u) = u^2/2 (minimum at 0) between a left
+    state a and a right state b:  F(a, b) = max(f(max(a, 0)), f(min(b, 0))).
+    It is piecewise smooth; Newton steps use the derivative of the branch that
+    attains the max (ties: the left state's branch), which is what makes the
+    iteration a semismooth Newton method.  Canonical rows, k-major, for
+    k = 0..Nt-2 and i = 0..Nx-1:
+      R_{k,i} = u_i^{k+1} - [ u_i^k - (dt/dx)(F_{i+1/2} - F_{i-1/2})
+                              + nu*dt*(u_{i+1} - 2u_i + u_{i-1})/dx^2 ]   (all at step k)
+    """
+    types = ("flux",)
+
+    def __init__(self, nx, nt, dt, dx, nu):
+        self.nx, self.nt = int(nx), int(nt)
+        self.dt, self.dx, self.nu = float(dt), float(dx), float(nu)
+        self.n = self.nx * self.nt
+        self.m = self.nx * (self.nt - 1)
+
+    @staticmethod
+    def flux(a, b):
+        """F, dF/da, dF/db, d2F/da2, d2F/db2 of Godunov's flux (elementwise)."""
+        ap, bm = np.maximum(a, 0.0), np.minimum(b, 0.0)
+        left = ap * ap >= bm * bm
+        F = np.where(left, 0.5 * ap * ap, 0.5 * bm * bm)
+        Fa = np.where(left, ap, 0.0)
+        Fb = np.where(left, 0.0, bm)
+        Faa = np.where(left & (a > 0.0), 1.0, 0.0)
+        Fbb = np.where(~left & (b < 0.0), 1.0, 0.0)
+        return F, Fa, Fb, Faa, Fbb
+
+    def h(self, u):
+        U = u.reshape(self.nt, self.nx)
+        r = self.dt / self.dx
+        v = self.nu * self.dt / (self.dx * self.dx)
+        out = np.empty((self.nt - 1, self.nx))
+        for k in range(self.nt - 1):
+            uk = U[k]
+            up, um = np.roll(uk, -1), np.roll(uk, 1)
+            Fp = self.flux(uk, up)[0]
+            Fm = self.flux(um, uk)[0]
+            out[k] = U[k + 1] - (uk - r * (Fp - Fm) + v * (up - 2.0 * uk + um))
+        return out.reshape(-1)
+
+    def jac(self, u):
+        U = u.reshape(self.nt, self.nx)
+        r = self.dt / self.dx
+        v = self.nu * self.dt / (self.dx * self.dx)
+        nx, nt = self.nx, self.nt
+        K, I = np.meshgrid(np.arange(nt - 1), np.arange(nx), indexing="ij")
+        row = K * nx + I
+        ip, im = (I + 1) % nx, (I - 1) % nx
+        _, Fa_p, Fb_p, _, _ = self.flux(U[K, I], U[K, ip])    # interface i+1/2
+        _, Fa_m, Fb_m, _, _ = self.flux(U[K, im], U[K, I])    # interface i-1/2
+        parts = [
+            (row, _vid1(nx, K + 1, I), np.ones_like(row, dtype=float)),
+            (row, _vid1(nx, K, I), -1.0 + r * (Fa_p - Fb_m) + 2.0 * v),
+            (row, _vid1(nx, K, ip), r * Fb_p - v),
+            (row, _vid1(nx, K, im), -r * Fa_m - v),
+        ]
+        rows = np.concatenate([p[0].ravel() for p in parts])
+        cols = np.concatenate([p[1].ravel() for p in parts])
+        vals = np.concatenate([p[2].ravel() for p in parts])
+        return sp.csr_matrix((vals, (rows, cols)), shape=(self.m, self.n))
+
+    def hess(self, u, lam):
+        # lam^T h: row (k, i) carries r*(F_{i+1/2} - F_{i-1/2}); each branch is
+        # a square of one state, so the Hessian is diagonal
+        U = u.reshape(self.nt, self.nx)
+        L = np.asarray(lam).reshape(self.nt - 1, self.nx)
+        r = self.dt / self.dx
+        d = np.zeros((self.nt, self.nx))
+        for k in range(self.nt - 1):
+            uk = U[k]
+            _, _, _, Faa_p, _ = self.flux(uk, np.roll(uk, -1))          # F(u_j, u_{j+1})
+            _, _, _, _, Fbb_m = self.flux(np.roll(uk, 1), uk)          # F(u_{j-1}, u_j)
+            # u_j enters F_{j+1/2} of rows j (+) and j+1 (-) as the left
+            # state, F_{j-1/2} of rows j (-) and j-1 (+) as the right state
+            d[k] = r * (Faa_p * (L[k] - np.roll(L[k], -1)) + Fbb_m * (np.roll(L[k], 1) - L[k]))
+        return sp.diags(d.reshape(-1))
+
+    def split(self, r):
+        return {"flux": r}
+
+
 class BurgersBC:
     """Boundary rows and global mass of the paper's first Burgers constraint
     regime (Appendix A, Burgers problem: the Dirichlet condition on the left
@@ -350,7 +444,7 @@ class BurgersBC:
 
 
 FAMILIES = {MASS_IC: MassIC, FISHER_KPP: FisherKPP, BURGERS_LF: BurgersLF,
-            DIFF2D_ENERGY: Diff2DEnergy, BURGERS_BC: BurgersBC}
+            DIFF2D_ENERGY: Diff2DEnergy, BURGERS_BC: BurgersBC, BURGERS_GODUNOV: BurgersGodunov}
 
 
 def family_of(sample, **kw):
@@ -367,6 +461,8 @@ def family_of(sample, **kw):
                             sample.p0, sample.aux)
     if f == BURGERS_BC:
         return BurgersBC(sample.nx, sample.nt, sample.dx, sample.aux[0], sample.aux[1])
+    if f == BURGERS_GODUNOV:
+        return BurgersGodunov(sample.nx, sample.nt, sample.dt, sample.dx, sample.p0)
     raise ValueError(f"unknown family {f}")
 
 

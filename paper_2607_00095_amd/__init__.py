@@ -11,7 +11,7 @@ The library must be built: importing this package without libsnap.so raises.
     u = SnapProject.apply(uhat, aux, plan)       # autograd: d u*/d u_hat
 """
 from .api import (  # noqa: F401
-    BURGERS_BC, BURGERS_LF, DIFF2D_ENERGY, FISHER_KPP, MASS_IC, PREC_FP64, PREC_MIXED, FLAG_KEEP_FACTOR,
+    BURGERS_BC, BURGERS_GODUNOV, BURGERS_LF, DIFF2D_ENERGY, FISHER_KPP, MASS_IC, PREC_FP64, PREC_MIXED, FLAG_KEEP_FACTOR,
     FLAG_GRAPH, FLAG_AUTOTUNE, FLAG_SOC, KERNEL_BAND_FACTOR, KERNEL_BAND_SOLVE,
     Options, Plan, SnapError, SnapProject, lib_path, pcfm_sample, project, project_backward,
     stats_to_numpy, status_name,

@@ -9,7 +9,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY, BURGERS_BC = 1, 2, 3, 4, 5
+MASS_IC, FISHER_KPP, BURGERS_LF, DIFF2D_ENERGY, BURGERS_BC, BURGERS_GODUNOV = 1, 2, 3, 4, 5, 6
 PREC_FP64, PREC_MIXED = 0, 1
 FLAG_KEEP_FACTOR, FLAG_GRAPH, FLAG_AUTOTUNE, FLAG_SOC = 1, 2, 4, 8
 KERNEL_BAND_FACTOR, KERNEL_BAND_SOLVE = 0, 1

@@ -140,7 +140,8 @@ int64_t rows_of(const snap_sample_desc& d) {
   switch (d.family) {
     case SNAP_MASS_IC:
     case SNAP_FISHER_KPP: return (int64_t)d.nx + d.nt - 1;
-    case SNAP_BURGERS_LF: return (int64_t)d.nx * (d.nt - 1);
+    case SNAP_BURGERS_LF:
+    case SNAP_BURGERS_GODUNOV: return (int64_t)d.nx * (d.nt - 1);
     case SNAP_DIFF2D_ENERGY: return (int64_t)d.nx * d.ny * (d.nt - 1) + d.nt;
     case SNAP_BURGERS_BC: return 3 * (int64_t)d.nt;
     default: return -1;
@@ -262,7 +263,7 @@ int tune_group(const snap_plan_s& p, const Group& g, const std::vector<int>& can
   Lcg rng{0x5eed5eedull};
   for (int i = 0; i < n; ++i) {
     const snap_sample_desc& q = d[i];
-    const bool burgers = q.family == SNAP_BURGERS_LF;
+    const bool burgers = q.family == SNAP_BURGERS_LF || q.family == SNAP_BURGERS_GODUNOV;
     for (int k = 0; k < q.nt; ++k)
       for (int x = 0; x < q.nx; ++x) {
         const double t = 6.283185307179586 * x / q.nx;
@@ -393,7 +394,7 @@ int snap_plan_create(snap_plan* out, int32_t batch, const snap_sample_desc* desc
       cls = slab_class(d.nx, d.nt);
       if (d.family == SNAP_FISHER_KPP && !(d.dt > 0.0)) cls = -1;
       cost[s] = (double)d.nx * d.nt;
-    } else if (d.family == SNAP_BURGERS_LF) {
+    } else if (d.family == SNAP_BURGERS_LF || d.family == SNAP_BURGERS_GODUNOV) {
       kind = 1;
       cls = (d.dt > 0.0 && d.dx > 0.0) ? band_class(d.nx, d.nt, mixed) : -1;
       if (cls > 0) need = band_workspace_bytes(d.nx, d.nt, mixed);

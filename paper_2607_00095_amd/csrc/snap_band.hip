@@ -103,6 +103,8 @@ struct BandShared {
 struct Ctx {
   int nx, nt, m, n, M, NB;
   double q, c, cd;           // f-coefficient dt/(2dx), diffusion number, -1 + 2c
+  bool god;                  // Godunov's interface flux (else Lax-Friedrichs)
+  double sg, cv;             // Godunov form: dt/dx and nu dt/dx^2
   bool bwd;
   const double* uh;          // u_hat (forward)
   const double* g;           // upstream gradient (backward)
@@ -176,20 +178,72 @@ __device__ __forceinline__ double gres(const Ctx& C, int k, int x) {
   return C.bwd ? -C.g[v] : C.u[v] - C.uh[v] + jt_at(C, C.lam, k, x);
 }
 
-// W at variable (k, x) from the current multipliers
-__device__ __forceinline__ double w_at(const Ctx& C, int k, int x) {
+// Godunov's flux of the convex f(u) = u^2/2 (paper Appendix D, Godunov's
+// flux conservation) between a left state a and a right state b:
+// F = max(f(max(a, 0)), f(min(b, 0))).  Newton steps differentiate the branch
+// that attains the max (ties: the left state's), so F_a, F_b, F_aa, F_bb are
+// the generalized derivatives of a semismooth Newton step; each branch is a
+// square of one state, which keeps the Lagrangian Hessian diagonal.
+struct GFlux {
+  double F, Fa, Fb, Faa, Fbb;
+};
+__device__ __forceinline__ GFlux gflux(double a, double b) {
+  const double ap = fmax(a, 0.0), bm = fmin(b, 0.0);
+  GFlux g;
+  if (ap * ap >= bm * bm) {
+    g.F = 0.5 * ap * ap; g.Fa = ap; g.Fb = 0.0; g.Faa = a > 0.0 ? 1.0 : 0.0; g.Fbb = 0.0;
+  } else {
+    g.F = 0.5 * bm * bm; g.Fa = 0.0; g.Fb = bm; g.Faa = 0.0; g.Fbb = b < 0.0 ? 1.0 : 0.0;
+  }
+  return g;
+}
+
+// Godunov form: coefficients of row (k, x) on u(k, x-1), u(k, x), u(k, x+1)
+// from slab k (U); fm / fp are the fluxes at x - 1/2 and x + 1/2
+struct GRow {
+  double cl, c0, cr;
+};
+__device__ __forceinline__ GRow grow_of(const Ctx& C, const GFlux& fm, const GFlux& fp) {
+  return GRow{-C.sg * fm.Fa - C.cv, -1.0 + C.sg * (fp.Fa - fm.Fb) + 2.0 * C.cv, C.sg * fp.Fb - C.cv};
+}
+__device__ __forceinline__ GRow grow(const Ctx& C, const double* U, int x) {
+  const double u0 = U[x];
+  return grow_of(C, gflux(U[wrap(x - 1, C.nx)], u0), gflux(u0, U[wrap(x + 1, C.nx)]));
+}
+// coefficient of u(k, y) in row (k, y-1), row (k, y) and row (k, y+1)
+__device__ __forceinline__ GRow gcol(const Ctx& C, const double* U, int y) {
+  const double u0 = U[y];
+  const GFlux fm = gflux(U[wrap(y - 1, C.nx)], u0), fp = gflux(u0, U[wrap(y + 1, C.nx)]);
+  return GRow{C.sg * fm.Fb - C.cv, -1.0 + C.sg * (fp.Fa - fm.Fb) + 2.0 * C.cv, -C.sg * fp.Fa - C.cv};
+}
+
+// W at variable (k, x) from the current multipliers, before the floor
+__device__ __forceinline__ double w_raw(const Ctx& C, int k, int x) {
   if (k > C.nt - 2) return 1.0;
   const double* L = C.lam + (size_t)k * C.nx;
-  double w = 1.0 + C.q * (L[wrap(x - 1, C.nx)] - L[wrap(x + 1, C.nx)]);
-  return fmax(w, kWFloor);
+  const int xm = wrap(x - 1, C.nx), xp = wrap(x + 1, C.nx);
+  if (C.god) {
+    const double* U = C.u + (size_t)k * C.nx;
+    const double u0 = U[x];
+    const GFlux fm = gflux(U[xm], u0), fp = gflux(u0, U[xp]);
+    return 1.0 + C.sg * (fp.Faa * (L[x] - L[xp]) + fm.Fbb * (L[xm] - L[x]));
+  }
+  return 1.0 + C.q * (L[xm] - L[xp]);
+}
+
+__device__ __forceinline__ double w_at(const Ctx& C, int k, int x) { return fmax(w_raw(C, k, x), kWFloor); }
+
+// h of row (k, x) given slab k's three values and u(k+1, x)
+__device__ __forceinline__ double h_of(const Ctx& C, double um, double u0, double up, double un) {
+  if (C.god)
+    return un - u0 + C.sg * (gflux(u0, up).F - gflux(um, u0).F) - C.cv * (up - 2.0 * u0 + um);
+  return un - u0 + 0.5 * C.q * (up * up - um * um) - C.c * (up - 2.0 * u0 + um);
 }
 
 // h of row (k, x)
 __device__ __forceinline__ double h_row(const Ctx& C, int k, int x) {
   const double* U = C.u + (size_t)k * C.nx;
-  const double up = U[wrap(x + 1, C.nx)], um = U[wrap(x - 1, C.nx)], u0 = U[x];
-  return C.u[(size_t)(k + 1) * C.nx + x] - u0 + 0.5 * C.q * (up * up - um * um) -
-         C.c * (up - 2.0 * u0 + um);
+  return h_of(C, U[wrap(x - 1, C.nx)], U[x], U[wrap(x + 1, C.nx)], C.u[(size_t)(k + 1) * C.nx + x]);
 }
 
 // (J^T y)(k, x) for a row-space vector y in canonical order
@@ -198,8 +252,12 @@ __device__ __forceinline__ double jt_at(const Ctx& C, const double* y, int k, in
   double s = 0.0;
   if (k >= 1) s += y[(size_t)(k - 1) * nx + x];
   if (k <= C.nt - 2) {
-    const double uu = C.u[(size_t)k * nx + x];
     const double* Y = y + (size_t)k * nx;
+    if (C.god) {
+      const GRow g = gcol(C, C.u + (size_t)k * nx, x);
+      return s + g.cl * Y[wrap(x - 1, nx)] + g.c0 * Y[x] + g.cr * Y[wrap(x + 1, nx)];
+    }
+    const double uu = C.u[(size_t)k * nx + x];
     s += (C.q * uu - C.c) * Y[wrap(x - 1, nx)];     // row (k, x-1): its +1 neighbour is x
     s += C.cd * Y[x];
     s += (-C.q * uu - C.c) * Y[wrap(x + 1, nx)];    // row (k, x+1): its -1 neighbour is x
@@ -213,6 +271,10 @@ __device__ __forceinline__ double j_at(const Ctx& C, const double* z, int k, int
   const double* U = C.u + (size_t)k * nx;
   const double* Z = z + (size_t)k * nx;
   const int xp = wrap(x + 1, nx), xm = wrap(x - 1, nx);
+  if (C.god) {
+    const GRow g = grow(C, U, x);
+    return z[(size_t)(k + 1) * nx + x] + g.c0 * Z[x] + g.cr * Z[xp] + g.cl * Z[xm];
+  }
   return z[(size_t)(k + 1) * nx + x] + C.cd * Z[x] + (C.q * U[xp] - C.c) * Z[xp] +
          (-C.q * U[xm] - C.c) * Z[xm];
 }
@@ -273,6 +335,7 @@ __device__ void assemble_rows(const Ctx& C, const WsLayout& WL, int r0, int r1, 
     }
     const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
     double rhs = C.bwd ? 0.0 : h_row(C, k, x);
+    const GRow gr = C.god ? grow(C, C.u + (size_t)k * nx, x) : GRow{0.0, 0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       // the four variables of row (k, x): (k+1, x), (k, x), (k, x+1), (k, x-1)
@@ -280,19 +343,27 @@ __device__ void assemble_rows(const Ctx& C, const WsLayout& WL, int r0, int r1, 
       const int y = (e <= 1) ? x : (e == 2 ? wrap(x + 1, nx) : wrap(x - 1, nx));
       const size_t v = (size_t)kk * nx + y;
       const double uy = C.u[v];
-      const double al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
+      const bool up = kk >= 1, own = kk <= C.nt - 2;
+      double al, cm, c0, cp;    // J(r, v); J of rows (kk, y-1), (kk, y), (kk, y+1) at v
+      if (C.god) {
+        al = (e == 0) ? 1.0 : (e == 1 ? gr.c0 : (e == 2 ? gr.cr : gr.cl));
+        const GRow gc = own ? gcol(C, C.u + (size_t)kk * nx, y) : GRow{0.0, 0.0, 0.0};
+        cm = gc.cl; c0 = gc.c0; cp = gc.cr;
+      } else {
+        al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
+        cm = C.q * uy - C.c; c0 = C.cd; cp = -C.q * uy - C.c;
+      }
       const double sv = al / w_at(C, kk, y);
       rhs -= sv * gres(C, kk, y);
       // rows touching variable (kk, y): (kk-1, y) with 1; (kk, y-1), (kk, y), (kk, y+1)
-      const bool up = kk >= 1, own = kk <= C.nt - 2;
       col[4 * e + 0] = up ? (kk - 1) * nx + pos_of(y, nx) : r;
       val[4 * e + 0] = up ? sv : 0.0;
       col[4 * e + 1] = own ? kk * nx + pos_of(wrap(y - 1, nx), nx) : r;
-      val[4 * e + 1] = own ? sv * (C.q * uy - C.c) : 0.0;
+      val[4 * e + 1] = own ? sv * cm : 0.0;
       col[4 * e + 2] = own ? kk * nx + pos_of(y, nx) : r;
-      val[4 * e + 2] = own ? sv * C.cd : 0.0;
+      val[4 * e + 2] = own ? sv * c0 : 0.0;
       col[4 * e + 3] = own ? kk * nx + pos_of(wrap(y + 1, nx), nx) : r;
-      val[4 * e + 3] = own ? sv * (-C.q * uy - C.c) : 0.0;
+      val[4 * e + 3] = own ? sv * cp : 0.0;
     }
     if (rhs_out) {
       rvec[(size_t)k * nx + x] = rhs;
@@ -318,12 +389,14 @@ __device__ void assemble_rhs_rows(const Ctx& C, const WsLayout& WL, int r0, int 
     if (r >= C.m) { rin[r] = 0.0; continue; }
     const int k = r / nx, px = r - k * nx, x = fold_x(px, nx);
     double rhs = h_row(C, k, x);
+    const GRow gr = C.god ? grow(C, C.u + (size_t)k * nx, x) : GRow{0.0, 0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int kk = (e == 0) ? k + 1 : k;
       const int y = (e <= 1) ? x : (e == 2 ? wrap(x + 1, nx) : wrap(x - 1, nx));
       const double uy = C.u[(size_t)kk * nx + y];
-      const double al = (e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c));
+      const double al = C.god ? ((e == 0) ? 1.0 : (e == 1 ? gr.c0 : (e == 2 ? gr.cr : gr.cl)))
+                              : ((e == 0) ? 1.0 : (e == 1 ? C.cd : (e == 2 ? C.q * uy - C.c : -C.q * uy - C.c)));
       rhs -= al / w_at(C, kk, y) * gres(C, kk, y);
     }
     rvec[(size_t)k * nx + x] = rhs;
@@ -1066,6 +1139,9 @@ __device__ __forceinline__ Ctx make_ctx(const KernelArgs& A, const snap_sample_d
   C.q = 0.5 * D.dt / D.dx;
   C.c = D.p1 * D.dt / (2.0 * D.dx) + D.p0 * D.dt / (D.dx * D.dx);
   C.cd = -1.0 + 2.0 * C.c;
+  C.god = D.family == SNAP_BURGERS_GODUNOV;
+  C.sg = D.dt / D.dx;
+  C.cv = D.p0 * D.dt / (D.dx * D.dx);
   C.bwd = bwd;
   C.uh = A.uhat ? A.uhat + D.var_off : nullptr;
   C.g = A.grad_u ? A.grad_u + D.var_off : nullptr;
@@ -1289,7 +1365,7 @@ __device__ __forceinline__ double h_trial(const Ctx& C, const double* pv, double
   const double up = C.u[b0 + xp] + alpha * pv[b0 + xp];
   const double um = C.u[b0 + xm] + alpha * pv[b0 + xm];
   const double un = C.u[b0 + C.nx + x] + alpha * pv[b0 + C.nx + x];
-  return un - u0 + 0.5 * C.q * (up * up - um * um) - C.c * (up - 2.0 * u0 + um);
+  return h_of(C, um, u0, up, un);
 }
 
 // ||h||_1 at u + alpha p
@@ -1504,9 +1580,16 @@ __device__ void adjoint_rhs_rows(const Ctx& C, const WsLayout& WL, int r0, int r
       const int xp = wrap(x + 1, C.nx), xm = wrap(x - 1, C.nx);
       const double* U = C.u + (size_t)k * C.nx;
       double s = C.g[(size_t)(k + 1) * C.nx + x] / w_at(C, k + 1, x);
-      s += C.cd * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
-      s += (C.q * U[xp] - C.c) * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
-      s += (-C.q * U[xm] - C.c) * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
+      if (C.god) {
+        const GRow g = grow(C, U, x);
+        s += g.c0 * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
+        s += g.cr * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
+        s += g.cl * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
+      } else {
+        s += C.cd * C.g[(size_t)k * C.nx + x] / w_at(C, k, x);
+        s += (C.q * U[xp] - C.c) * C.g[(size_t)k * C.nx + xp] / w_at(C, k, xp);
+        s += (-C.q * U[xm] - C.c) * C.g[(size_t)k * C.nx + xm] / w_at(C, k, xm);
+      }
       v = s;
       rvec[(size_t)k * C.nx + x] = s;
     }
@@ -1523,10 +1606,7 @@ __device__ void adjoint_finish(const KernelArgs& A, const Ctx& C, const snap_sam
   for (int v = threadIdx.x; v < C.n; v += NW * kWave) {
     const int k = v / C.nx, x = v - k * C.nx;
     A.grad_uhat[D.var_off + v] = (C.g[v] - jt_at(C, lamp, k, x)) / w_at(C, k, x);
-    if (k <= C.nt - 2) {
-      const double* L = C.lam + (size_t)k * C.nx;
-      floored |= 1.0 + C.q * (L[wrap(x - 1, C.nx)] - L[wrap(x + 1, C.nx)]) < kWFloor;
-    }
+    if (k <= C.nt - 2) floored |= w_raw(C, k, x) < kWFloor;
   }
   floored = __syncthreads_or(floored);
   if (threadIdx.x == 0) {

@@ -21,6 +21,8 @@ Families (the integer codes match the C header):
   5  BURGERS_BC  Dirichlet row on the left boundary, mass row and Neumann row
                  on the right boundary per time step (Appendix A, the first
                  Burgers regime; Appendix D discretizations)
+  6  BURGERS_GODUNOV  local flux-update residuals of Burgers with Godunov's
+                 flux (Appendix D, Godunov's flux conservation), periodic
 
 Every field is float64.  Layout of one sample: time slab major, then y, then x
 (x fastest), which is the paper's flattening of the space-time grid
@@ -38,15 +40,17 @@ F2_FISHER_KPP = 2
 F3_BURGERS_LF = 3
 F4_DIFF2D_ENERGY = 4
 F5_BURGERS_BC = 5
+F6_BURGERS_GODUNOV = 6
 
-FAMILY_NAMES = {1: "mass_ic", 2: "fisher_kpp", 3: "burgers_lf", 4: "diff2d_energy", 5: "burgers_bc"}
+FAMILY_NAMES = {1: "mass_ic", 2: "fisher_kpp", 3: "burgers_lf", 4: "diff2d_energy", 5: "burgers_bc",
+                6: "burgers_godunov"}
 
 
 def n_rows(family: int, nx: int, ny: int, nt: int) -> int:
     """Number of constraint rows of one sample, canonical encoding."""
     if family in (F1_MASS_IC, F2_FISHER_KPP):
         return nx + nt - 1
-    if family == F3_BURGERS_LF:
+    if family in (F3_BURGERS_LF, F6_BURGERS_GODUNOV):
         return nx * (nt - 1)
     if family == F4_DIFF2D_ENERGY:
         return (nt - 1) * nx * ny + nt
@@ -60,7 +64,7 @@ def n_aux(family: int, nx: int, ny: int, nt: int) -> int:
         return nx + 1          # g[nx], M0
     if family == F2_FISHER_KPP:
         return nx              # g[nx]
-    if family == F3_BURGERS_LF:
+    if family in (F3_BURGERS_LF, F6_BURGERS_GODUNOV):
         return 0
     if family == F4_DIFF2D_ENERGY:
         return nt              # E[nt]
@@ -252,6 +256,36 @@ def _draw_f5(rng, nx, nt, noise=0.05) -> Sample:
                   aux=np.array([u_left, m0]))
 
 
+def _godunov_periodic_update(u, dt, dx, nu):
+    """One explicit step of Burgers with Godunov's interface flux and a
+    centred viscous term, periodic in x (input synthesis only)."""
+    up = np.roll(u, -1)
+    a, b = np.maximum(u, 0.0), np.minimum(up, 0.0)
+    flux_half = np.maximum(0.5 * a * a, 0.5 * b * b)                   # F_{i+1/2}
+    visc = nu * (up - 2.0 * u + np.roll(u, 1)) / (dx * dx)
+    return u - (dt / dx) * (flux_half - np.roll(flux_half, 1)) + dt * visc
+
+
+def _draw_f6(rng, nx, nt, dt=1e-3, nu=0.0, noise=0.02) -> Sample:
+    # random four-mode Fourier initial condition (it changes sign, so the
+    # trajectory holds shocks, expansions and the flux's kinks), scaled to
+    # max |u| = 0.8, explicit Godunov steps plus N(0, noise^2) per step
+    x = np.arange(nx) / nx
+    u0 = np.zeros(nx)
+    for k in range(1, 5):
+        a, b = rng.standard_normal(2)
+        u0 += (a * np.cos(2 * np.pi * k * x) + b * np.sin(2 * np.pi * k * x)) / k
+    u0 *= 0.8 / max(np.abs(u0).max(), 1e-12)
+    dx = 1.0 / nx
+    traj = np.empty((nt, nx))
+    traj[0] = u0
+    xi = noise * rng.standard_normal((nt - 1, nx))
+    for k in range(nt - 1):
+        traj[k + 1] = _godunov_periodic_update(traj[k], dt, dx, nu) + xi[k]
+    return Sample(F6_BURGERS_GODUNOV, nx, 1, nt, dt=dt, dx=dx, p0=nu,
+                  uhat=traj, aux=np.zeros(0))
+
+
 def _draw_f4(rng, n, nt, dt=0.01, noise=0.05) -> Sample:
     kappa = rng.uniform(0.01, 0.1)
     h = 1.0 / n
@@ -303,6 +337,11 @@ def burgers_batch(batch=512, nx=128, nt=128, dt=1e-3, nu=0.01, alpha=1.0, seed=3
 def burgers_bc_batch(batch=512, nx=101, nt=101, seed=6001) -> Batch:
     rng = _rng(seed)
     return Batch([_draw_f5(rng, nx, nt) for _ in range(batch)], name="burgers_bc").pack()
+
+
+def godunov_batch(batch=512, nx=101, nt=11, dt=0.005, nu=0.0, seed=7001) -> Batch:
+    rng = _rng(seed)
+    return Batch([_draw_f6(rng, nx, nt, dt=dt, nu=nu) for _ in range(batch)], name="burgers_godunov").pack()
 
 
 def diff2d_batch(batch=128, n=64, nt=16, dt=0.01, seed=4001) -> Batch:
@@ -357,6 +396,9 @@ CONFIGS = {
     "ragged": dict(fn=ragged_batch, kw=dict(batch=1024, seed=5001)),
     # the paper's first Burgers regime (boundary rows + mass) on its 101 x 101 grid
     "burgers_bc": dict(fn=burgers_bc_batch, kw=dict(batch=512, nx=101, nt=101, seed=6001)),
+    # the flux-residual rows of the paper's Godunov regime with ten flux steps
+    # (its Flux(10) case) on the paper's 101-point grid
+    "burgers_godunov": dict(fn=godunov_batch, kw=dict(batch=512, nx=101, nt=11, dt=0.005, seed=7001)),
 }
 
 
