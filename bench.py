@@ -409,7 +409,7 @@ def main():
         if name == "burgers_godunov":
             # the paper's constraint-count study on its Godunov regime: one,
             # five and ten flux steps (IC and mass rows are not part of this family)
-            sweep = []
+            fsweep = []
             for k in (1, 5, 10):
                 bk = synthgen.make(name, nt=k + 1)
                 pk = snap.Plan.from_batch(bk)
@@ -424,9 +424,9 @@ def main():
                 stk = snap.stats_to_numpy(sk_, len(bk))
                 hvk = max_violation(bk, uk_.cpu().numpy())
                 okk = int(((stk["status"] == 0) & (hvk <= H_FEAS)).sum())
-                sweep.append({"flux_steps": k, "rows_per_sample": bk.samples[0].m,
-                              "ms_per_step": seck * 1e3, "projected": okk, "value": okk / seck})
-            out["flux_steps_sweep"] = sweep
+                fsweep.append({"flux_steps": k, "rows_per_sample": bk.samples[0].m,
+                               "ms_per_step": seck * 1e3, "projected": okk, "value": okk / seck})
+            out["flux_steps_sweep"] = fsweep
 
         # the constrained flow-matching sampler around the projection: N
         # substeps of shoot -> project (plain FP64, one plan and workspace for
