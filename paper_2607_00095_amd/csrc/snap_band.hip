@@ -82,6 +82,9 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
 
 template <int BB, int NW, typename R>
 struct BandShared {
@@ -695,25 +698,28 @@ __device__ __attribute__((always_inline)) int factor_sweep(const Ctx& C, const W
       // backward.  (Lanes 32..63 repeat lanes 0..31.)
       const int k = fresh_v(lane & (kT - 1));  // (not hoisted: 16 identity values would be)
       const bool xl = (lane & 16) != 0;        // an identity / X lane
+      // The elimination runs in the factor's precision R: an FP32 factor
+      // (refined in FP64 by its solves) takes FP32 pivots, one readlane per
+      // broadcast value instead of two.
       double dmine = 1.0;
       int nonpos = 0;
-      double v[kT];
+      R v[kT];
 #pragma unroll
-      for (int i = 0; i < kT; ++i) v[i] = xl ? (i == k ? 1.0 : 0.0) : (double)sh.P[0][i * kLd + k];
+      for (int i = 0; i < kT; ++i) v[i] = xl ? (i == k ? (R)1 : (R)0) : sh.P[0][i * kLd + k];
       const double zk = sh.ring[(J % (BB + 1)) * kT + k];   // z(J), final
       R* Lgd = Lg + ((size_t)sl * (BB + 1)) * 256;
 #pragma unroll
       for (int p = 0; p < kT; ++p) {
-        const double dp = lane_bcast(v[p], p);   // A[p][p]
-        nonpos |= !(dp > 0.0);
-        const double rdp = rcp_nr(dp);
+        const R dp = lane_bcast(v[p], p);        // A[p][p]
+        nonpos |= !(dp > (R)0);
+        const R rdp = rcp_nr(dp);
         if (k == p) dmine = dp;
-        const double m = v[p] * rdp;             // A lanes: L[k][p] = A[p][k] / D_p (symmetry)
+        const R m = v[p] * rdp;                  // A lanes: L[k][p] = A[p][k] / D_p (symmetry)
 #pragma unroll
         for (int i = p + 1; i < kT; ++i) v[i] -= lane_bcast(v[i], p) * m;
         if (xl && lane < 32) {                   // row p of X is final
-          sh.T[k * kLd + p] = (R)(v[p] * rdp);   // T[k][p] = X[p][k] / D_p
-          sh.X[p * kLd + k] = (R)v[p];
+          sh.T[k * kLd + p] = v[p] * rdp;        // T[k][p] = X[p][k] / D_p
+          sh.X[p * kLd + k] = v[p];
         }
       }
       if (lane < kT) {
