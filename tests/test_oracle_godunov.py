@@ -60,6 +60,29 @@ def test_flux_differences_telescope():
     np.testing.assert_allclose(R.sum(axis=1), U[1:].sum(axis=1) - U[:-1].sum(axis=1), atol=1e-12)
 
 
+def test_ic_flux_and_mass_rows_are_rank_deficient():
+    # The paper's Godunov regime stacks IC rows, flux-update rows and mass rows
+    # m(t_k) - m(t_0).  IC and flux rows alone are Nx*Nt rows on Nx*Nt
+    # unknowns and fix u; the mass rows add Nt-1 rows that are combinations of
+    # them on a periodic grid, so the stacked Jacobian has rank Nx*Nt and
+    # S = J J^T (W = I) is singular: the reason that regime is not projected.
+    rng = np.random.default_rng(11)
+    nx, nt = 7, 4
+    fam = BurgersGodunov(nx, nt, 0.01, 1 / nx, 0.0)
+    u = _away_from_kinks(fam, rng)
+    ic = np.eye(fam.n)[:nx]
+    mass = np.zeros((nt - 1, fam.n))
+    for k in range(1, nt):
+        mass[k - 1, k * nx:(k + 1) * nx] = fam.dx
+        mass[k - 1, :nx] = -fam.dx
+    jf = fam.jac(u).toarray()
+    square = np.vstack([ic, jf])
+    assert square.shape == (fam.n, fam.n) and np.linalg.matrix_rank(square) == fam.n
+    stacked = np.vstack([ic, jf, mass])
+    assert np.linalg.matrix_rank(stacked) == fam.n < stacked.shape[0]
+    assert np.linalg.matrix_rank(stacked @ stacked.T) == fam.n
+
+
 def _away_from_kinks(fam, rng, margin=0.05):
     # states with |u| > margin (away from the sonic point) and no interface
     # near a zero-speed shock (a > 0 > b with a = -b), where the branches tie
