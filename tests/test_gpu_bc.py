@@ -17,9 +17,12 @@ if not torch.cuda.is_available():
 import paper_2607_00095_amd as snap  # noqa: E402
 from gpu_helpers import check_samples, gpu_backward, gpu_project, oracle_solution, rel_err  # noqa: E402
 
-# every x-register count of a lane (nx up to 64 .. 512), the smallest grid,
-# one time step, slab counts that do not fill the four wavefronts evenly
-CASES = [(3, 1), (4, 2), (64, 3), (65, 7), (101, 101), (200, 13), (333, 9), (512, 5)]
+# every launch class on both sides of its edges (16-lane groups with 1, 2, 4
+# or 8 x registers per lane up to nx = 128, whole-wavefront groups with 4 or 8
+# above), the smallest grid, one time step, and slab counts that do not fill
+# the eight wavefronts evenly
+CASES = [(3, 1), (4, 2), (16, 3), (17, 4), (32, 6), (33, 2), (64, 3), (65, 7), (101, 101), (128, 3), (129, 2),
+         (200, 13), (256, 3), (257, 2), (333, 9), (512, 5)]
 
 
 @pytest.mark.parametrize("nx,nt", CASES)
